@@ -1,0 +1,248 @@
+/*
+ * rl_oracle.c -- plain, slow, obviously correct FP64 CPU oracle for Richardson-Lucy
+ * deconvolution and its thinned (selective) variant.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load this library.  The product path (the HIP library and its Python
+ * binding) never includes, links or calls anything in this directory, and this file
+ * includes nothing of the product path.
+ *
+ * What it computes (notation of the paper):
+ *   - blur model and problem statement f ~ u*h              (Section 1, eq. 1-2)
+ *   - RL: u^0 = f, u^{k+1} = (h^* * (f / (u^k*h))) . u^k      (Section 2, eq. 3)
+ *     where h^* is h reflected about the origin, so h^* * r is the correlation of r
+ *     with h                                                  (Section 2, text after eq. 3)
+ *   - boundary: every missing pixel is replaced by an image pixel (Section 2, "Boundary
+ *     treatment").  Two readings are offered:
+ *       BC_REFLECT   half-sample symmetric continuation (c b a | a b c), period 2N;
+ *       BC_REPLICATE the closest image pixel (constant continuation), the paper's rule.
+ *   - thinned RL: active pixels get fresh v^k and u^{k+1}; inactive pixels keep v^{k-1}
+ *     (here: keep their ratio r) and u^k; every R-th iteration all pixels are active
+ *     (Section 4, eq. 4-5 and the reset rule after them).
+ *
+ * Conventions: images are row-major H x W; the PSF is kh x kw with origin
+ * (oy, ox) = (kh/2, kw/2), so tap h[i][j] sits at offset (i-oy, j-ox).
+ *   conv(u)(y,x) = sum_{i,j} h[i][j] * u[fold(y-(i-oy))][fold(x-(j-ox))]
+ *   corr(r)(y,x) = sum_{i,j} h[i][j] * r[fold(y+(i-oy))][fold(x+(j-ox))]
+ * Sums run over i ascending, then j ascending; zero taps are skipped (exact).
+ * r = f / v where v > 0, else 0 (the paper does not say what happens at v = 0).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (see build_oracle.py).
+ * -ffp-contract=off keeps every product and sum a separately rounded FP64 operation.
+ * OpenMP only splits the image rows among threads; every pixel's sum is computed by one
+ * thread in the order above, so the result does not depend on the thread count.
+ *
+ * ORACLE_MUTANT (compile-time, default 0) plants one deliberate mistake.  It exists only
+ * so the test suite can show that its pins catch each kind of mistake.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
+enum { BC_REFLECT = 0, BC_REPLICATE = 1 };
+enum { THIN_OFF = 0, THIN_ABS = 1, THIN_REL = 2 };
+
+/* ---- boundary fold (Section 2, "Boundary treatment") -------------------------------- */
+long oracle_fold(long i, long n, int bc)
+{
+    if (bc == BC_REPLICATE) {
+        if (i < 0) return 0;
+        if (i >= n) return n - 1;
+        return i;
+    }
+    long p = i % (2 * n);
+    if (p < 0) p += 2 * n;
+#if ORACLE_MUTANT == 1
+    /* planted: whole-sample mirror (c b | a b c) instead of half-sample */
+    if (n > 1) { p = i % (2 * n - 2); if (p < 0) p += 2 * n - 2; return p < n ? p : 2 * n - 2 - p; }
+    return 0;
+#else
+    return p < n ? p : 2 * n - 1 - p;
+#endif
+}
+
+/* ---- one output of the forward convolution u*h at (y,x) (Section 1, eq. 2) ----------- */
+static double conv_at(const double *u, long H, long W, const double *h, int kh, int kw,
+                      int bc, long y, long x)
+{
+    const int oy = kh / 2, ox = kw / 2;
+    double s = 0.0;
+    for (int i = 0; i < kh; ++i) {
+        for (int j = 0; j < kw; ++j) {
+#if ORACLE_MUTANT == 2
+            double w = h[j * kh + i]; /* planted: transposed PSF (only differs if kh==kw) */
+            if (kh != kw) w = h[i * kw + j];
+#else
+            double w = h[i * kw + j];
+#endif
+#if ORACLE_MUTANT == 3
+            if (i == kh - 1 && j == kw - 1) continue; /* planted: last tap dropped */
+#endif
+            if (w == 0.0) continue;
+            long sy = oracle_fold(y - (i - oy), H, bc);
+            long sx = oracle_fold(x - (j - ox), W, bc);
+            s += w * u[sy * W + sx];
+        }
+    }
+    return s;
+}
+
+/* ---- one output of the adjoint h^* * r at (y,x) (Section 2, eq. 3) -------------------- */
+static double corr_at(const double *r, long H, long W, const double *h, int kh, int kw,
+                      int bc, long y, long x)
+{
+    const int oy = kh / 2, ox = kw / 2;
+    double s = 0.0;
+    for (int i = 0; i < kh; ++i) {
+        for (int j = 0; j < kw; ++j) {
+            double w = h[i * kw + j];
+            if (w == 0.0) continue;
+#if ORACLE_MUTANT == 4
+            long sy = oracle_fold(y - (i - oy), H, bc); /* planted: h instead of h^* */
+            long sx = oracle_fold(x - (j - ox), W, bc);
+#else
+            long sy = oracle_fold(y + (i - oy), H, bc);
+            long sx = oracle_fold(x + (j - ox), W, bc);
+#endif
+            s += w * r[sy * W + sx];
+        }
+    }
+    return s;
+}
+
+void oracle_conv(const double *u, int H, int W, const double *h, int kh, int kw, int bc,
+                 double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x)
+            out[y * W + x] = conv_at(u, H, W, h, kh, kw, bc, y, x);
+}
+
+void oracle_corr(const double *r, int H, int W, const double *h, int kh, int kw, int bc,
+                 double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x)
+            out[y * W + x] = corr_at(r, H, W, h, kh, kw, bc, y, x);
+}
+
+/* ratio f / (u*h), guarded: a non-positive denominator gives 0 */
+static double ratio(double f, double v)
+{
+#if ORACLE_MUTANT == 5
+    return f > 0.0 ? v / f : 0.0; /* planted: inverted ratio */
+#else
+    return v > 0.0 ? f / v : 0.0;
+#endif
+}
+
+static double update(double u, double c)
+{
+#if ORACLE_MUTANT == 6
+    (void)u;
+    return c; /* planted: the multiplicative factor u^k is dropped */
+#else
+    return u * c;
+#endif
+}
+
+/*
+ * Plain RL (Section 2, eq. 3): K iterations from u (in/out; the caller sets u^0, usually f).
+ * Work arrays v and r of H*W doubles are supplied by the caller.
+ */
+void oracle_rl(const double *f, double *u, int H, int W, const double *h, int kh, int kw,
+               int bc, int K, double *r)
+{
+    const long N = (long)H * W;
+    for (int k = 0; k < K; ++k) {
+#pragma omp parallel for schedule(static)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x)
+                r[y * W + x] = ratio(f[y * W + x], conv_at(u, H, W, h, kh, kw, bc, y, x));
+#pragma omp parallel for schedule(static)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x)
+                u[y * W + x] = update(u[y * W + x], corr_at(r, H, W, h, kh, kw, bc, y, x));
+        (void)N;
+    }
+}
+
+/*
+ * The convergence test of thinned RL, taken in single precision on the float32 values of
+ * u^{k+1} (a) and u^k (b) (Section 4: "absolute changes ... below a given threshold").
+ * ABS: |a-b| < tau;  REL: |a-b| < tau*b.  tau <= 0 never freezes; a pixel that stays 0
+ * counts as converged.  Every operation is one correctly rounded float32 operation.
+ */
+int oracle_below(float a, float b, int mode, float tau)
+{
+    if (!(tau > 0.0f)) return 0;
+    if (b == 0.0f && a == 0.0f) return 1;
+    volatile float d = a - b; /* volatile: keep the float32 rounding of each step */
+    float ad = fabsf(d);
+    volatile float t = (mode == THIN_REL) ? tau * b : tau;
+#if ORACLE_MUTANT == 7
+    return ad <= t * 2.0f; /* planted: threshold doubled */
+#else
+    return ad < t;
+#endif
+}
+
+/*
+ * One thinned RL iteration k (Section 4, eq. 4-5, reset rule after them).
+ *   full  = (k == 0) or (R > 0 and k mod R == 0): every pixel is active;
+ *   else  pixel p is active iff cnt[p] < hyst.
+ * Active pixels: r = f / (u^k*h) (guarded); then u^{k+1} = u^k . (h^* * r), where inactive
+ * neighbours contribute their stale r; then the float32 convergence test updates cnt
+ * (below: cnt = min(cnt+1, 255), else cnt = 0).  Inactive pixels keep u, r and cnt.
+ * u, r, cnt are in/out.  u_prev is a caller-supplied H*W work array.
+ * Returns the number of active pixels |A_k|.
+ */
+long oracle_thin_step(const double *f, double *u, double *r, uint8_t *cnt, int H, int W,
+                      const double *h, int kh, int kw, int bc, long k, int mode, float tau,
+                      int hyst, int reset_period, double *u_prev)
+{
+    const long N = (long)H * W;
+    const int full = (k == 0) || (reset_period > 0 && k % reset_period == 0);
+    long n_active = 0;
+    for (long p = 0; p < N; ++p) {
+        u_prev[p] = u[p];
+        if (full || cnt[p] < hyst) ++n_active;
+    }
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            long p = y * W + x;
+            if (full || cnt[p] < hyst)
+                r[p] = ratio(f[p], conv_at(u_prev, H, W, h, kh, kw, bc, y, x));
+        }
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            long p = y * W + x;
+            if (!(full || cnt[p] < hyst)) continue;
+            double un = update(u_prev[p], corr_at(r, H, W, h, kh, kw, bc, y, x));
+            u[p] = un;
+            if (mode != THIN_OFF) {
+                int below = oracle_below((float)un, (float)u_prev[p], mode, tau);
+                cnt[p] = below ? (uint8_t)(cnt[p] < 255 ? cnt[p] + 1 : 255) : 0;
+            }
+        }
+    return n_active;
+}
+
+/* Sum in row-major order (used for the flux sum(u)). */
+double oracle_sum(const double *a, long n)
+{
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += a[i];
+    return s;
+}
+
+int oracle_mutant(void) { return ORACLE_MUTANT; }

@@ -1,0 +1,323 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these checks re-types the oracle's own formulas: each compares it with a library
+routine (scipy.ndimage, numpy.fft, numpy.pad), a closed form, an invariant, an exact
+rational brute force on tiny inputs, or a value/trend the paper prints.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RNG = np.random.default_rng(12345)
+
+
+def _asym_psfs():
+    return [synth.dense_random(5, 3), synth.oblique_line(11, 30.0), synth.dense_random(3, 9),
+            synth.box_h(7), synth.box_v(5), synth.disc(4),
+            np.array([[0.0, 0.25, 0.0], [0.5, 0.125, 0.0], [0.0, 0.0, 0.125]], np.float32)]
+
+
+# ---- P1: convolution / correlation == scipy.ndimage (library routine) -------------------
+@pytest.mark.parametrize("bc,mode", [("reflect", "reflect"), ("replicate", "nearest")])
+@pytest.mark.parametrize("shape", [(37, 53), (5, 3), (1, 9), (12, 1)])
+def test_p1_conv_corr_match_scipy(orc, bc, mode, shape):
+    u = RNG.uniform(0.05, 1.0, shape)
+    for h in _asym_psfs():
+        h64 = h.astype(np.float64)
+        ref_c = ndimage.convolve(u, h64, mode=mode)
+        ref_r = ndimage.correlate(u, h64, mode=mode)
+        np.testing.assert_allclose(orc.conv(u, h64, bc), ref_c, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(orc.corr(u, h64, bc), ref_r, rtol=1e-13, atol=1e-15)
+
+
+# ---- P6: brute force with numpy.pad continuation, tiny images, deep folds, even sizes ----
+@pytest.mark.parametrize("bc,padmode", [("reflect", "symmetric"), ("replicate", "edge")])
+def test_p6_bruteforce_tiny_deep_folds(orc, bc, padmode):
+    for H in range(1, 6):
+        for W in range(1, 7):
+            u = RNG.integers(0, 256, size=(H, W)).astype(np.float64)
+            for (kh, kw) in [(1, 1), (1, 2), (2, 1), (3, 4), (1, 11), (9, 1), (4, 4), (2, 13)]:
+                h = RNG.integers(0, 4, size=(kh, kw)).astype(np.float64)
+                oy, ox = kh // 2, kw // 2
+                P = 20
+                up = np.pad(u, P, mode=padmode)
+                ref_c = np.zeros((H, W))
+                ref_r = np.zeros((H, W))
+                for i in range(kh):
+                    for j in range(kw):
+                        dy, dx = i - oy, j - ox
+                        ref_c += h[i, j] * up[P - dy:P - dy + H, P - dx:P - dx + W]
+                        ref_r += h[i, j] * up[P + dy:P + dy + H, P + dx:P + dx + W]
+                # integer data and weights: every sum is exact in FP64
+                assert np.array_equal(orc.conv(u, h, bc), ref_c), (H, W, kh, kw)
+                assert np.array_equal(orc.corr(u, h, bc), ref_r), (H, W, kh, kw)
+
+
+def test_fold_matches_numpy_pad(orc):
+    for n in range(1, 7):
+        i = np.arange(-25, n + 25)
+        sym = np.pad(np.arange(n), 25, mode="symmetric")
+        edge = np.pad(np.arange(n), 25, mode="edge")
+        assert [orc.fold(k, n, "reflect") for k in i] == list(sym)
+        assert [orc.fold(k, n, "replicate") for k in i] == list(edge)
+
+
+# ---- P12: direct convolution == FFT convolution of the padded image (library routine) ---
+def test_p12_conv_matches_fft(orc):
+    u = RNG.uniform(0.0, 1.0, (64, 48))
+    for h in [synth.disc(7), synth.oblique_line(21, 65.0), synth.dense_random(15, 1)]:
+        h64 = h.astype(np.float64)
+        kh, kw = h.shape
+        oy, ox = kh // 2, kw // 2
+        up = np.pad(u, ((kh - 1 - oy, oy), (kw - 1 - ox, ox)), mode="symmetric")
+        Hp, Wp = up.shape
+        F = np.fft.rfft2(up) * np.fft.rfft2(h64, s=(Hp, Wp))
+        full = np.fft.irfft2(F, s=(Hp, Wp))
+        ref = full[kh - 1:kh - 1 + u.shape[0], kw - 1:kw - 1 + u.shape[1]]
+        np.testing.assert_allclose(orc.conv(u, h64), ref, rtol=0, atol=1e-12)
+
+
+# ---- P2: delta PSF is the identity (closed form) ------------------------------------------
+@pytest.mark.parametrize("bc", ["reflect", "replicate"])
+def test_p2_delta_identity(orc, bc):
+    f = synth.observe(synth.latent_image(40, 33, 3), synth.delta(), "poisson", 3)
+    u = orc.rl(f, synth.delta(), 7, bc)
+    assert np.array_equal(u, f.astype(np.float64))
+
+
+# ---- P3: 1x1 image and constant images (closed forms) -----------------------------------
+@pytest.mark.parametrize("bc", ["reflect", "replicate"])
+def test_p3_single_pixel_and_constant(orc, bc):
+    for h in _asym_psfs():
+        f = np.array([[0.37]], np.float32)
+        u0 = np.array([[0.81]])
+        u1 = orc.rl(f, h, 1, bc, u0=u0)
+        assert abs(u1[0, 0] - float(f[0, 0])) < 1e-15
+        c = np.full((9, 14), 0.25, np.float32)
+        np.testing.assert_allclose(orc.rl(c, h, 5, bc), 0.25, rtol=1e-14)
+
+
+# ---- P4: u = g is a fixed point when f = g*h exactly (blur made by scipy) ----------------
+@pytest.mark.parametrize("bc,mode", [("reflect", "reflect"), ("replicate", "nearest")])
+def test_p4_fixed_point(orc, bc, mode):
+    g = synth.latent_image(48, 40, 4)
+    for h in _asym_psfs():
+        h64 = h.astype(np.float64)
+        f = ndimage.convolve(g, h64, mode=mode)
+        u = orc.rl(f, h64, 6, bc, u0=g)
+        # first step: r = f/(g*h) = 1 and h^* * 1 = s = sum(h) at every pixel, so u^1 = s g;
+        # later steps: r = 1/s, h^* * r = 1, so u^K = s g for all K >= 1 (the float32 taps
+        # sum to 1 only up to a few ulp)
+        np.testing.assert_allclose(u, g * h64.sum(), rtol=1e-12)
+
+
+# ---- P5: flux preservation (invariant) ---------------------------------------------------
+def test_p5_flux_reflect_symmetric(orc):
+    f = synth.observe(synth.latent_image(50, 61, 5), synth.disc(5), "poisson", 5)
+    for h in [synth.disc(5), synth.box_h(9), synth.box_v(13), synth.box_rect(3, 5)]:
+        u = orc.rl(f, h, 20, "reflect")
+        assert abs(u.sum() - f.astype(np.float64).sum()) < 1e-11 * f.sum()
+
+
+def test_p5_flux_zero_margin_any_psf(orc):
+    f = np.zeros((60, 64))
+    f[15:45, 16:48] = RNG.uniform(0.1, 1.0, (30, 32))
+    for h in [synth.oblique_line(11, 30.0), synth.dense_random(7, 2)]:
+        # support stays away from the border for these few iterations: K * radius < margin
+        u = orc.rl(f, h, 2, "reflect")
+        assert abs(u.sum() - f.sum()) < 1e-12 * f.sum()
+
+
+# ---- P7: adjointness <u*h, r> = <u, h^* * r> (invariant) --------------------------------
+def test_p7_adjoint(orc):
+    u = RNG.uniform(0, 1, (31, 29))
+    r = RNG.uniform(0, 1, (31, 29))
+    for h in [synth.disc(4), synth.box_h(9), synth.box_rect(5, 3)]:
+        lhs = np.vdot(orc.conv(u, h), r)
+        rhs = np.vdot(u, orc.corr(r, h))
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # asymmetric PSF away from the border
+    u2 = np.zeros((40, 40))
+    u2[12:28, 12:28] = RNG.uniform(0, 1, (16, 16))
+    r2 = np.zeros((40, 40))
+    r2[12:28, 12:28] = RNG.uniform(0, 1, (16, 16))
+    h = synth.dense_random(7, 5)
+    assert abs(np.vdot(orc.conv(u2, h), r2) - np.vdot(u2, orc.corr(r2, h))) < 1e-12
+
+
+# ---- exact rational brute force of plain RL on tiny inputs --------------------------------
+def _exact_rl(f, h, K, padmode):
+    H, W = f.shape
+    kh, kw = h.shape
+    oy, ox = kh // 2, kw // 2
+    P = 12
+    yi = np.pad(np.arange(H), P, mode=padmode)
+    xi = np.pad(np.arange(W), P, mode=padmode)
+    F = [[Fraction(float(f[y, x])) for x in range(W)] for y in range(H)]
+    Hf = [[Fraction(float(h[i, j])) for j in range(kw)] for i in range(kh)]
+    u = [row[:] for row in F]
+    for _ in range(K):
+        r = [[None] * W for _ in range(H)]
+        for y in range(H):
+            for x in range(W):
+                v = sum((Hf[i][j] * u[yi[P + y - (i - oy)]][xi[P + x - (j - ox)]]
+                         for i in range(kh) for j in range(kw)), Fraction(0))
+                r[y][x] = F[y][x] / v if v > 0 else Fraction(0)
+        u = [[u[y][x] * sum((Hf[i][j] * r[yi[P + y + (i - oy)]][xi[P + x + (j - ox)]]
+                             for i in range(kh) for j in range(kw)), Fraction(0))
+              for x in range(W)] for y in range(H)]
+    return np.array([[float(v) for v in row] for row in u])
+
+
+@pytest.mark.parametrize("bc,padmode", [("reflect", "symmetric"), ("replicate", "edge")])
+def test_exact_rational_rl_tiny(orc, bc, padmode):
+    f = np.array([[0.5, 0.25, 1.0, 0.0], [0.75, 0.125, 0.5, 0.375], [1.0, 0.625, 0.25, 0.5]],
+                 np.float32)
+    for h in [np.array([[0.25, 0.5, 0.125, 0.125]], np.float32),
+              np.array([[0.0, 0.25], [0.5, 0.125], [0.125, 0.0]], np.float32),
+              np.array([[0.5], [0.25], [0.25], [0.0], [0.0]], np.float32)]:
+        ref = _exact_rl(f, h, 2, padmode)
+        np.testing.assert_allclose(orc.rl(f, h, 2, bc), ref, rtol=1e-14, atol=1e-300)
+
+
+# ---- thinning: the float32 convergence test on hand-picked values (closed form) -----------
+def test_below_closed_form(orc):
+    e = 2.0 ** -13
+    # ABS: |a-b| < tau, strict
+    assert not orc.below(1.0 + e, 1.0, "abs", e)
+    assert orc.below(1.0 + e, 1.0, "abs", e * 1.5)
+    assert orc.below(1.0, 1.0 + e, "abs", e * 1.5)
+    # REL: |a-b| < tau * b
+    assert orc.below(4.0 + 4 * e, 4.0, "rel", 1.5 * e)
+    assert not orc.below(4.0 + 4 * e, 4.0, "rel", e)
+    assert not orc.below(2.0, 1.0, "abs", 0.5)
+    # tau = 0 never freezes, even an unchanged pixel; a pixel stuck at zero is converged
+    assert not orc.below(1.0, 1.0, "abs", 0.0)
+    assert orc.below(0.0, 0.0, "rel", 1e-4)
+    assert orc.below(0.5, 0.5, "rel", 1e-4)
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---- thinning schedule, closed form with the delta PSF -------------------------------------
+def test_thin_schedule_delta_closed_form(orc):
+    rows = _golden_rows("thin_schedule_delta.txt")
+    f = synth.observe(synth.latent_image(12, 17, 6), synth.delta(), "poisson", 6)
+    N = f.size
+    for hyst, row in zip((5, 1), rows):
+        want = np.array([int(v) for v in row]) * N
+        out = orc.rl_thin(f, synth.delta(), len(want), dict(mode="rel", tau=1e-4,
+                          hysteresis=hyst, reset_period=10, compact_period=10))
+        assert np.array_equal(out["active"], want)
+        assert np.array_equal(out["u"], f.astype(np.float64))
+
+
+# ---- P8: threshold 0 is exactly plain RL (Table 2, first two rows) -------------------------
+@pytest.mark.parametrize("mode", ["abs", "rel"])
+def test_p8_tau_zero_is_plain(orc, mode):
+    h = synth.disc(3)
+    f = synth.observe(synth.latent_image(30, 26, 7), h, "poisson", 7)
+    plain = orc.rl(f, h, 12)
+    th = orc.rl_thin(f, h, 12, dict(mode=mode, tau=0.0, hysteresis=1, reset_period=10,
+                                     compact_period=1))
+    assert np.array_equal(th["u"], plain)
+    assert (th["active"] == f.size).all()
+
+
+# ---- P9: omitted fraction bounded by the reset rule, monotone in tau (Table 2 trends) ------
+def test_p9_table2_trends(orc):
+    rows = _golden_rows("table2_trends.txt")
+    omitted_paper = [float(r[1]) for r in rows]
+    assert omitted_paper[0] == 0.0 and max(omitted_paper) < 90.0
+    assert all(b >= a for a, b in zip(omitted_paper, omitted_paper[1:]))
+    h = synth.disc(4)
+    f = synth.observe(synth.latent_image(48, 48, 8), h, "poisson", 8)
+    ref = orc.rl(f, h, 100)
+    prev_omit, prev_err = -1.0, -1.0
+    for tau in [0.0, 0.005, 0.02, 0.1, 0.5]:
+        # paper mode: absolute threshold on the 0..255 grey scale, images scaled to [0, 1]
+        th = orc.rl_thin(f, h, 100, dict(mode="abs", tau=tau / 255.0, hysteresis=1,
+                                          reset_period=10, compact_period=1))
+        omit = 100.0 * (1.0 - th["active"].sum() / (100 * f.size))
+        err = float(np.abs(th["u"] - ref).max())
+        assert omit < 90.0
+        assert omit >= prev_omit
+        assert err >= prev_err
+        prev_omit, prev_err = omit, err
+    assert prev_omit > 50.0
+
+
+# ---- P10: disc support sizes (Table 1 / Section 5 reading) --------------------------------
+def test_p10_disc_support():
+    for r, n in _golden_rows("disc_support.txt"):
+        h = synth.disc(int(r))
+        assert np.count_nonzero(h) == int(n)
+        ints, _ = oracle.psf_runs(h)
+        assert len(ints) == 2 * int(r) + 1
+        # half-width of row dy is floor(sqrt(r^2 - dy^2))
+        for dy, x0, x1 in ints:
+            hw = int(np.floor(np.sqrt(int(r) ** 2 - dy * dy)))
+            assert (x0, x1) == (-hw, hw)
+
+
+def test_psf_runs_definition():
+    h = np.array([[0, 1, 1, 2, 0, 3], [0, 0, 0, 0, 0, 0], [5, 5, 5, 5, 5, 5]], np.float32)
+    ints, ws = oracle.psf_runs(h)
+    assert ints.tolist() == [[-1, -2, -1], [-1, 0, 0], [-1, 2, 2], [1, -3, 2]]
+    assert ws.tolist() == [1.0, 2.0, 3.0, 5.0]
+
+
+def test_rebuild_schedule():
+    ks = [k for k in range(35) if oracle.is_rebuild(k, 10, 10)]
+    assert ks == [1, 11, 21, 31]
+    ks = [k for k in range(13) if oracle.is_rebuild(k, 10, 1)]
+    assert ks == [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 12]
+    ks = [k for k in range(25) if oracle.is_rebuild(k, 0, 10)]
+    assert ks == [1, 11, 21]
+
+
+# ---- mutation check: every planted mistake in the oracle is caught by some pin ------------
+def _pins_pass(o):
+    """A compact subset of the pins above, run against an oracle variant."""
+    u = RNG.uniform(0.05, 1.0, (11, 13))
+    try:
+        for h in _asym_psfs()[:3] + [_asym_psfs()[-1]]:
+            h64 = h.astype(np.float64)
+            if not np.allclose(o.conv(u, h64), ndimage.convolve(u, h64, mode="reflect"),
+                               rtol=1e-13):
+                return False
+            if not np.allclose(o.corr(u, h64), ndimage.correlate(u, h64, mode="reflect"),
+                               rtol=1e-13):
+                return False
+            f = ndimage.convolve(u, h64, mode="reflect")
+            if not np.allclose(o.rl(f, h64, 3, u0=u), u * h64.sum(), rtol=1e-12):
+                return False
+        e = 2.0 ** -13
+        if o.below(1.0 + e, 1.0, "abs", e) or not o.below(1.0 + e, 1.0, "abs", 1.5 * e):
+            return False
+        if o.below(4.0 + 4 * e, 4.0, "rel", e) or not o.below(4.0 + 4 * e, 4.0, "rel", 1.5 * e):
+            return False
+    except Exception:
+        return False
+    return True
+
+
+def test_planted_mistakes_are_caught():
+    assert _pins_pass(oracle.Oracle(0))
+    for m in range(1, 8):
+        assert not _pins_pass(oracle.Oracle(m)), f"mutant {m} passed the pins"
