@@ -1,0 +1,229 @@
+/*
+ * rl.h -- C ABI of the MI355X Richardson-Lucy library (librl.so).
+ *
+ * The library solves the non-blind deconvolution problem "given the blurred image f and
+ * the point-spread function h, find u with f ~ u*h" (Section 1, eq. 2) by Richardson-Lucy
+ * iteration (Section 2, eq. 3):
+ *
+ *     u^0 = f,    u^{k+1} = (h^* * (f / (u^k * h))) . u^k
+ *
+ * where h^* is h reflected about the origin, so h^* * r is the correlation of r with h.
+ * Every step of every iteration runs in the library's own HIP kernels on the GPU.
+ *
+ * Conventions used by every call below
+ * ------------------------------------
+ *  Images   row-major float32, height x width, pitch = width, pixel (y, x) at y*width + x.
+ *  PSF      row-major float32 psf_h x psf_w in HOST memory, origin at
+ *           (psf_h / 2, psf_w / 2); tap h[i][j] sits at offset (i - psf_h/2, j - psf_w/2).
+ *             (u*h)(y,x)   = sum_ij h[i][j] u[fold(y-(i-oy))][fold(x-(j-ox))]
+ *             (h^* * r)(y,x) = sum_ij h[i][j] r[fold(y+(i-oy))][fold(x+(j-ox))]
+ *  Ratio    r = f / v where v = u^k*h > 0, else r = 0.
+ *  Boundary missing pixels are replaced by image pixels (Section 2, "Boundary treatment"):
+ *             RL_BC_REFLECT   half-sample symmetric continuation (c b a | a b c), period 2N
+ *             RL_BC_REPLICATE the closest image pixel (the paper's rule)
+ *           Both fold to any depth, so PSFs larger than the image are allowed.
+ *  Memory   The caller owns every buffer.  Device pointers (f, u0, u_out, workspace, state
+ *           buffers) must come from hipMalloc (or torch) on the current HIP device.  The
+ *           library never allocates device memory: all per-job device state lives in the
+ *           caller's workspace, whose size rl_workspace_bytes() reports exactly.
+ *  Streams  Every device operation of a job is enqueued on the hipStream_t given in
+ *           rl_params.stream (NULL = the null stream).  Calls return before the GPU work
+ *           finishes unless stated otherwise.
+ *  Errors   Every call returns an rl_status; nothing is thrown across the ABI.  After
+ *           RL_E_DEVICE the job must be destroyed.
+ *  Threads  One host thread at a time per job; distinct jobs are independent.
+ *  Determinism  The same inputs give bit-identical results, alone or batched.
+ */
+#ifndef RL_H
+#define RL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rl_status;
+#define RL_OK 0
+#define RL_E_INVAL (-1)       /* bad argument: sizes, PSF, workspace, f, call arguments  */
+#define RL_E_NOMEM (-2)       /* workspace too small                                      */
+#define RL_E_DEVICE (-3)      /* a HIP runtime call failed                                */
+#define RL_E_STATE (-4)       /* call not allowed in this state (e.g. after destroy)      */
+#define RL_E_UNSUPPORTED (-5) /* valid request this build does not serve                  */
+
+/* boundary continuation */
+#define RL_BC_REFLECT 0
+#define RL_BC_REPLICATE 1
+
+/* convolution path (Section 3): which operator family evaluates u*h and h^* * r */
+#define RL_PATH_AUTO 0     /* chosen from the PSF by the PSF compiler                      */
+#define RL_PATH_DIRECT 1   /* per-tap sum over the non-zero taps (naive / list filter)     */
+#define RL_PATH_BOX_AXIS 2 /* 1 x L or L x 1 uniform box: sliding window (Section 3)       */
+#define RL_PATH_RUNS 3     /* per-row runs: sliding for uniform runs (generic box filter),
+                              register-blocked spans for non-uniform rows (list filter)    */
+
+/* iteration schedule: how the per-iteration kernels are organised */
+#define RL_SCHED_AUTO 0
+#define RL_SCHED_TWO_PASS 1 /* conv+ratio kernel, then corr+update kernel, per iteration   */
+#define RL_SCHED_RESIDENT 2 /* BOX_AXIS only: independent lines held on chip for all
+                               iterations of one rl_iterate call                           */
+
+/* thinning (Section 4) */
+#define RL_THIN_OFF 0
+#define RL_THIN_ABS 1 /* frozen when |u^{k+1} - u^k| < tau        (the paper's rule)   */
+#define RL_THIN_REL 2 /* frozen when |u^{k+1} - u^k| < tau * u^k  (relative variant)   */
+
+typedef struct rl_thin {
+    int32_t mode;           /* RL_THIN_*                                                  */
+    float tau;              /* threshold, > 0 to freeze anything                          */
+    int32_t hysteresis;     /* H: frozen after H consecutive tests below tau (H >= 1)     */
+    int32_t reset_period;   /* R: iteration k is full when k == 0 or k % R == 0; 0 = never */
+    int32_t compact_period; /* C: the active list is rebuilt after each full step and when
+                               (k - 1) % C == 0                                           */
+} rl_thin;
+
+/* Kernel-shape knobs (0 = let the library choose).  Results do not depend on them beyond
+ * float32 rounding order.  strip: outputs per lane of the tiled kernels (8, 16 or 32);
+ * seg: pixels per lane of the resident solver (2..32, power of two); lines_per_wg: image
+ * lines per workgroup of the resident solver. */
+typedef struct rl_tuning {
+    int32_t strip, seg, lines_per_wg, reserved;
+} rl_tuning;
+
+typedef struct rl_params {
+    int32_t height, width;  /* image size, both >= 1                                      */
+    const float *f;         /* DEVICE, height*width, >= 0 and finite; copied at rl_init   */
+    int32_t psf_h, psf_w;   /* PSF size, each in [1, 127]                                 */
+    const float *psf;       /* HOST, psf_h*psf_w, >= 0, finite, positive sum; copied      */
+    const float *u0;        /* DEVICE initial estimate or NULL for u^0 = f; copied        */
+    int32_t boundary;       /* RL_BC_*                                                    */
+    int32_t path;           /* RL_PATH_*                                                  */
+    int32_t schedule;       /* RL_SCHED_*                                                 */
+    int32_t kahan;          /* 1: per-row partial sums combined with Kahan compensation
+                               and compensated running sums; 0: plain float32 sums        */
+    rl_thin thin;           /* thinning; mode RL_THIN_OFF disables it                     */
+    void *stream;           /* hipStream_t for every device operation of the job          */
+    rl_tuning tuning;       /* kernel-shape knobs, zero-initialise for defaults           */
+} rl_params;
+
+typedef struct rl_stats {
+    int64_t iters_done;       /* k: iterations applied so far                             */
+    int64_t active_now;       /* pixels active in the next iteration (N without thinning) */
+    int64_t skipped_px_iters; /* sum over iterations of (N - |A_k|)                       */
+    double flux;              /* sum of u^k, reduced on the GPU in FP64 in a fixed order  */
+    int32_t path;             /* RL_PATH_* actually used                                  */
+    int32_t schedule;         /* RL_SCHED_* actually used                                 */
+    int32_t f_invalid;        /* 1 if f had a negative or non-finite value                */
+    int32_t reserved;
+} rl_stats;
+
+typedef struct rl_job rl_job;
+
+/* Status name, e.g. "RL_E_INVAL".  Never NULL. */
+const char *rl_status_str(rl_status s);
+
+/*
+ * Exact number of device bytes rl_init needs for these parameters (f, u and r planes,
+ * the compiled PSF, thinning state, reduction scratch).  Pure host computation.
+ * Returns RL_E_INVAL for invalid sizes or PSF (PSF values are read from p->psf).
+ */
+rl_status rl_workspace_bytes(const rl_params *p, size_t *bytes);
+
+/*
+ * Validate p, compile the PSF (host), and enqueue on p->stream: the upload of the compiled
+ * PSF, the copy of f (and u0) into the workspace, and zeroing of the thinning state.
+ * ws: caller-owned device buffer of ws_bytes >= rl_workspace_bytes(p), 256-byte aligned;
+ * it must stay alive and untouched until rl_destroy.  f's sign and finiteness are checked
+ * on the GPU; the outcome is reported by rl_result (RL_E_INVAL) and in rl_stats.f_invalid.
+ * On success *out receives a new job handle (host memory owned by the library).
+ * Errors: RL_E_INVAL (sizes, PSF, NULL pointers, path not applicable to the PSF),
+ * RL_E_NOMEM (ws_bytes too small), RL_E_DEVICE.
+ */
+rl_status rl_init(const rl_params *p, void *ws, size_t ws_bytes, rl_job **out);
+
+/* Enqueue n_iter >= 0 further RL iterations (Section 2, eq. 3; thinned per Section 4 when
+ * p->thin.mode != RL_THIN_OFF).  Asynchronous. */
+rl_status rl_iterate(rl_job *job, int32_t n_iter);
+
+/*
+ * Enqueue a device-to-device copy of u^k into u_out (height*width floats, may be NULL to
+ * skip).  If st is non-NULL, also reduce the statistics on the GPU, synchronise the job's
+ * stream and fill *st.  Returns RL_E_INVAL if f was found invalid (only known once the
+ * stream has been synchronised, i.e. when st != NULL).
+ */
+rl_status rl_result(rl_job *job, float *u_out, rl_stats *st);
+
+/* Release the host handle.  The workspace stays with the caller.  Never fails on a valid
+ * handle; the handle is invalid afterwards.  Does not synchronise. */
+rl_status rl_destroy(rl_job *job);
+
+/*
+ * Batched iteration: enqueue n_iter[j] iterations of every job j in ONE stream, with
+ * each iteration's kernels covering all jobs that still have iterations left in one
+ * launch per phase.  Jobs must have been created with thinning off and the two-pass
+ * schedule (any path).  The per-launch work tables live in the batch workspace:
+ *   rl_batch_workspace_bytes(jobs, n_jobs, &bytes), then rl_iterate_batch(..., bws, bytes).
+ * Results per job are bit-identical to rl_iterate on that job alone.
+ */
+rl_status rl_batch_workspace_bytes(rl_job *const *jobs, int32_t n_jobs, size_t *bytes);
+rl_status rl_iterate_batch(rl_job *const *jobs, const int32_t *n_iter, int32_t n_jobs,
+                           void *bws, size_t bws_bytes, void *stream);
+
+/*
+ * Lock-step / checkpoint hooks (enqueued on the job's stream, asynchronous):
+ *   rl_get_state copies u^k, the persistent ratio r (thinned mode keeps stale values of
+ *   inactive pixels) and the per-pixel convergence counters out of the workspace, and
+ *   writes k to *k_out (host).  Any of u, r, cnt may be NULL.
+ *   rl_set_state copies them in and sets the iteration counter to k (so the thinning
+ *   schedule continues from k).  NULL skips a buffer (r and cnt are then left as they are).
+ * Buffers: u, r: height*width float32 (device); cnt: height*width uint8 (device).
+ */
+rl_status rl_get_state(rl_job *job, float *u, float *r, uint8_t *cnt, int64_t *k_out);
+rl_status rl_set_state(rl_job *job, const float *u, const float *r, const uint8_t *cnt,
+                       int64_t k);
+
+/*
+ * Thinned mode: the compacted active-pixel list of the last rebuild (ascending row-major
+ * indices p with cnt[p] < hysteresis, Section 4), copied into list_dev (device int32,
+ * capacity cap entries); *n receives the list length (synchronises the stream).
+ */
+rl_status rl_active_list(rl_job *job, int32_t *list_dev, int64_t cap, int64_t *n);
+
+/* Thinned mode: the number of active pixels |A_k| of the last min(k, cap, 4096)
+ * iterations, oldest first, into out (host int64); *n receives the count.  Synchronises. */
+rl_status rl_thin_schedule(rl_job *job, int64_t *out, int32_t cap, int32_t *n);
+
+/*
+ * PSF compiler (host only, no device work): classify the PSF and build its integer run
+ * list -- per PSF row i ascending, maximal spans of consecutive columns with non-zero,
+ * bit-identical weights (the representation behind the paper's generic box and list
+ * filters, Section 3).  runs (int32, 3 per run): dy = i - oy, x0, x1 (column offsets
+ * j - ox of the first and last tap); w: the float32 weight of each run.  *cls receives the
+ * RL_PATH_* that RL_PATH_AUTO would choose.  Returns RL_E_NOMEM if cap < number of runs
+ * (*n_runs is still set), RL_E_INVAL for an invalid PSF.
+ */
+rl_status rl_psf_runs(const float *psf, int32_t psf_h, int32_t psf_w, int32_t *runs,
+                      float *w, int32_t cap, int32_t *n_runs, int32_t *cls);
+
+/* Kernel timing for measurement: while enabled, every kernel launch of every job is
+ * bracketed by HIP events on the stream it is launched on.  rl_timing_read synchronises
+ * on the recorded events and reports, for the kernel named `name`, the number of launches
+ * and their summed duration in milliseconds; rl_timing_reset discards the records. */
+rl_status rl_timing_enable(int32_t on);
+rl_status rl_timing_read(const char *name, int64_t *launches, double *total_ms);
+rl_status rl_timing_reset(void);
+
+/* Describes the kernel configuration chosen for a job (for logs and tests):
+ * path, schedule, tile height/width, strip length, spans, taps. */
+typedef struct rl_job_info {
+    int32_t path, schedule, tile_h, tile_w, strip, n_spans, n_taps, lmax;
+    int32_t halo_y0, halo_y1, halo_x0, halo_x1;
+    int64_t ws_bytes;
+} rl_job_info;
+rl_status rl_job_describe(rl_job *job, rl_job_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RL_H */

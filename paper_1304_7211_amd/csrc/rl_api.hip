@@ -1,0 +1,895 @@
+// C ABI of the Richardson-Lucy library: job set-up, kernel selection and launch sequencing.
+// Every RL step runs in the kernels of rl_kernels.hpp; this file only decides which kernel,
+// with which tables and tiles, and enqueues them on the job's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psf_compile.hpp"
+#include "rl.h"
+#include "rl_kernels.hpp"
+
+using rlk::DevSpan;
+using rlk::PhaseArgs;
+using rlk::ResidentArgs;
+
+static_assert(sizeof(DevSpan) == sizeof(rl::Span), "span layout");
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kNW = 4;  // wavefronts per workgroup in the tiled kernels
+
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2 };
+
+// ---- kernel timing registry -----------------------------------------------------------
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+
+struct Config {
+    int path = 0, sched = 0, kind = 0, orient = 0, S = 16, lmax = 1;
+    int TA = 64, TB = 64, tiles_a = 1, tiles_b = 1;
+    // resident
+    int line_n = 0, lines = 0, wpl = 1, seg = 2, lines_per_wg = 1, line_words = 0;
+    size_t lds_a = 0, lds_b = 0;
+    rl::OpTable conv, corr;
+};
+
+struct Layout {
+    size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
+        bcounts, boffs, ctr, sched, red, red_i, total;
+};
+
+// counters block (int64 slots)
+enum Ctr { C_PLIST_LEN = 0, C_TLIST_LEN, C_ACTIVE_TOTAL, C_F_INVALID, C_ACTIVE_NOW, C_FLUX,
+           C_COUNT = 8 };
+
+int64_t thin_blocks(int64_t N) { return (N + 255) / 256; }
+
+bool is_full(int64_t k, int R) { return k == 0 || (R > 0 && k % R == 0); }
+bool is_rebuild(int64_t k, int R, int C) {
+    if (is_full(k, R)) return false;
+    return is_full(k - 1, R) || (C > 0 && (k - 1) % C == 0);
+}
+
+size_t tile_lds_bytes(const rl::OpTable& t, int orient, int TB, int extra) {
+    (void)orient;
+    size_t na = 64 + t.lane_max - t.lane_min;
+    size_t nb = TB + t.c_max - t.c_min + extra;
+    size_t ny = orient == rlk::ORIENT_ROWS ? na : nb;
+    size_t nx = orient == rlk::ORIENT_ROWS ? nb : na;
+    size_t pitch = nx | 1;
+    size_t main = ny * pitch * sizeof(float);
+    size_t stage = (size_t)64 * (TB + 1) * sizeof(float);
+    return std::max(main, stage);
+}
+
+// Cost estimate per output (VALU-op equivalents), used to pick kernel and orientation.
+double span_cost(const rl::OpTable& t, int S, int lmax, bool kahan) {
+    double valu = 0, lds = 0;
+    int lines = 0;
+    for (const rl::Span& s : t.spans) {
+        valu += lmax;
+        lds += double(S + lmax - 1) / S;
+        if (s.row_end) ++lines;
+    }
+    valu += lines * (kahan ? 4.0 : 1.0);
+    return std::max(valu, 2.0 * lds) + 8.0;
+}
+
+double slide_cost(const rl::OpTable& t, int S, bool kahan) {
+    double valu = 0, lds = 0;
+    for (const rl::Span& s : t.spans) {
+        valu += 2.0 + double(s.len) / S;
+        lds += 2.0 + double(s.len) / S;
+    }
+    valu += kahan ? 4.0 : 1.0;
+    return std::max(valu, 2.0 * lds) + 8.0;
+}
+
+bool all_uniform(const rl::OpTable& t) {
+    for (const rl::Span& s : t.spans)
+        if (!s.uniform) return false;
+    return true;
+}
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Decide path, schedule and kernel for a job.  Deterministic in (params, PSF).
+rl_status choose_config(const rl_params* p, const rl::CompiledPsf& c, Config* cfg,
+                        std::string* why) {
+    const int H = p->height, W = p->width;
+    const bool thin = p->thin.mode != RL_THIN_OFF;
+    int path = p->path == RL_PATH_AUTO ? c.auto_path : p->path;
+    if (path < RL_PATH_DIRECT || path > RL_PATH_RUNS) { *why = "unknown path"; return RL_E_INVAL; }
+    if (path == RL_PATH_BOX_AXIS && !c.is_axis_box) {
+        *why = "BOX_AXIS path needs a 1 x L or L x 1 uniform box PSF";
+        return RL_E_INVAL;
+    }
+    cfg->path = path;
+    int sched = p->schedule;
+    if (sched < RL_SCHED_AUTO || sched > RL_SCHED_RESIDENT) { *why = "unknown schedule"; return RL_E_INVAL; }
+    const int box_orient = c.box_orient == rl::Orient::Rows ? rlk::ORIENT_ROWS : rlk::ORIENT_COLS;
+    if (path == RL_PATH_BOX_AXIS && !thin && sched != RL_SCHED_TWO_PASS) {
+        int n = box_orient == rlk::ORIENT_ROWS ? W : H;
+        int m = box_orient == rlk::ORIENT_ROWS ? H : W;
+        // the on-chip halo holds a single reflection: needs L - 1 <= line length
+        if (n <= 8192 && c.box_len - 1 <= n) {
+            cfg->sched = RL_SCHED_RESIDENT;
+            cfg->kind = KIND_RESIDENT;
+            cfg->orient = box_orient;
+            cfg->line_n = n;
+            cfg->lines = m;
+            int seg_t = p->tuning.seg;
+            if (seg_t) {
+                if (seg_t < 2 || seg_t > 32 || (seg_t & (seg_t - 1))) { *why = "tuning.seg"; return RL_E_INVAL; }
+                cfg->seg = seg_t;
+                cfg->wpl = std::max(1, (n + 64 * seg_t - 1) / (64 * seg_t));
+                if (cfg->wpl > 4) { *why = "tuning.seg too small for this line"; return RL_E_INVAL; }
+            } else {
+                // default: 8 pixels per lane, at most 4 wavefronts per line
+                cfg->seg = 8;
+                cfg->wpl = (n + 64 * 8 - 1) / (64 * 8);
+                while (cfg->wpl > 4) { cfg->seg *= 2; cfg->wpl = (n + 64 * cfg->seg - 1) / (64 * cfg->seg); }
+                cfg->wpl = std::max(1, cfg->wpl);
+            }
+            const int tpl = 64 * cfg->wpl;
+            const int halo = c.box_len - 1;
+            const size_t span = (size_t)halo + n + halo + cfg->seg;
+            cfg->line_words = (int)(span + span / cfg->seg + 1);
+            const size_t per_line = 2 * (size_t)cfg->line_words * sizeof(float);
+            int by_threads = 256 / tpl;
+            int by_lds = (int)std::max<size_t>(1, (64 * 1024) / per_line);
+            int want = std::max(1, (m + 511) / 512);  // aim for >= 512 workgroups
+            if (p->tuning.lines_per_wg > 0) want = p->tuning.lines_per_wg;
+            cfg->lines_per_wg = std::max(1, std::min(std::min(by_threads, by_lds), want));
+            if (per_line > kLdsLimit) { *why = "line too long for LDS"; return RL_E_UNSUPPORTED; }
+            cfg->lds_a = cfg->lines_per_wg * per_line;
+            return RL_OK;
+        }
+        if (sched == RL_SCHED_RESIDENT) { *why = "line too long for the resident schedule"; return RL_E_UNSUPPORTED; }
+    }
+    if (sched == RL_SCHED_RESIDENT) {
+        *why = "the resident schedule serves BOX_AXIS PSFs without thinning";
+        return RL_E_UNSUPPORTED;
+    }
+    cfg->sched = RL_SCHED_TWO_PASS;
+    const float* h = p->psf;
+    const int kh = p->psf_h, kw = p->psf_w;
+    const bool kahan = p->kahan != 0;
+    const int64_t npx = (int64_t)H * W;
+    // outputs per lane: long strips amortise seeds and windows, short strips give the
+    // latency-bound kernels more wavefronts on small images
+    const int span_S = p->tuning.strip ? p->tuning.strip : (npx >= (int64_t)4 << 20 ? 16 : 8);
+    const int slide_S = p->tuning.strip ? p->tuning.strip : (npx >= (int64_t)4 << 20 ? 32 : 16);
+    if (span_S != 8 && span_S != 16 && span_S != 32) { *why = "tuning.strip"; return RL_E_INVAL; }
+    if (path == RL_PATH_DIRECT) {
+        cfg->kind = KIND_SPAN;
+        cfg->orient = rlk::ORIENT_ROWS;
+        cfg->S = std::min(span_S, 16);
+        cfg->lmax = 1;
+        cfg->conv = rl::build_tap_table(h, kh, kw, false);
+        cfg->corr = rl::build_tap_table(h, kh, kw, true);
+    } else if (path == RL_PATH_BOX_AXIS) {
+        cfg->kind = KIND_SLIDE;
+        cfg->orient = box_orient;
+        cfg->S = slide_S;
+        rl::Orient o = c.box_orient;
+        cfg->conv = rl::build_op_table(h, kh, kw, false, o, true, 0);
+        cfg->corr = rl::build_op_table(h, kh, kw, true, o, true, 0);
+    } else {
+        // RUNS: cheapest of {sliding runs, register-blocked spans} x {rows, cols}
+        double best = 1e30;
+        for (int oi = 0; oi < 2; ++oi) {
+            rl::Orient o = oi == 0 ? rl::Orient::Rows : rl::Orient::Cols;
+            rl::OpTable u = rl::build_op_table(h, kh, kw, false, o, true, 0);
+            if (all_uniform(u)) {
+                double cost = slide_cost(u, slide_S, kahan);
+                if (cost < best) {
+                    best = cost;
+                    cfg->kind = KIND_SLIDE;
+                    cfg->orient = oi;
+                    cfg->S = slide_S;
+                    cfg->lmax = 0;
+                }
+            }
+            for (int lm : {2, 4, 8, 16}) {
+                rl::OpTable t = rl::build_op_table(h, kh, kw, false, o, false, lm);
+                double cost = span_cost(t, std::min(span_S, 16), lm, kahan);
+                if (cost < best) {
+                    best = cost;
+                    cfg->kind = KIND_SPAN;
+                    cfg->orient = oi;
+                    cfg->S = std::min(span_S, 16);
+                    cfg->lmax = lm;
+                }
+            }
+        }
+        rl::Orient o = cfg->orient == 0 ? rl::Orient::Rows : rl::Orient::Cols;
+        bool split = cfg->kind == KIND_SLIDE;
+        int lm = cfg->kind == KIND_SLIDE ? 0 : cfg->lmax;
+        cfg->conv = rl::build_op_table(h, kh, kw, false, o, split, lm);
+        cfg->corr = rl::build_op_table(h, kh, kw, true, o, split, lm);
+    }
+    cfg->TA = 64;
+    cfg->TB = kNW * cfg->S;
+    int extra = cfg->kind == KIND_SPAN ? cfg->lmax - 1 : 0;
+    cfg->lds_a = tile_lds_bytes(cfg->conv, cfg->orient, cfg->TB, extra);
+    cfg->lds_b = tile_lds_bytes(cfg->corr, cfg->orient, cfg->TB, extra);
+    while (std::max(cfg->lds_a, cfg->lds_b) > kLdsLimit && cfg->kind == KIND_SLIDE && cfg->S > 8) {
+        cfg->S /= 2;
+        cfg->TB = kNW * cfg->S;
+        cfg->lds_a = tile_lds_bytes(cfg->conv, cfg->orient, cfg->TB, extra);
+        cfg->lds_b = tile_lds_bytes(cfg->corr, cfg->orient, cfg->TB, extra);
+    }
+    if (std::max(cfg->lds_a, cfg->lds_b) > kLdsLimit) {
+        *why = "PSF extent too large for the LDS tile";
+        return RL_E_UNSUPPORTED;
+    }
+    {
+        // the tile loader covers at most 64 * MAXC columns
+        const rl::OpTable& t = cfg->conv;
+        int nx = cfg->orient == rlk::ORIENT_ROWS
+                     ? cfg->TB + t.c_max - t.c_min + extra
+                     : 64 + t.lane_max - t.lane_min;
+        if (nx > 64 * rlk::MAXC) { *why = "PSF extent too wide for the tile loader"; return RL_E_UNSUPPORTED; }
+    }
+    const int la = cfg->orient == rlk::ORIENT_ROWS ? H : W;  // lane axis length
+    const int lb = cfg->orient == rlk::ORIENT_ROWS ? W : H;
+    cfg->tiles_a = (la + cfg->TA - 1) / cfg->TA;
+    cfg->tiles_b = (lb + cfg->TB - 1) / cfg->TB;
+    return RL_OK;
+}
+
+Layout make_layout(const rl_params* p, const Config& cfg) {
+    Layout L{};
+    const size_t N = (size_t)p->height * p->width;
+    const bool thin = p->thin.mode != RL_THIN_OFF;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.f = take(N * 4);
+    L.u = take(N * 4);
+    L.r = take(N * 4);
+    const size_t pad = 16;  // zero weights after the table (span kernel over-reads <= 15)
+    L.conv_spans = take(std::max<size_t>(1, cfg.conv.spans.size()) * sizeof(DevSpan));
+    L.conv_w = take((cfg.conv.w.size() + pad) * 4);
+    L.corr_spans = take(std::max<size_t>(1, cfg.corr.spans.size()) * sizeof(DevSpan));
+    L.corr_w = take((cfg.corr.w.size() + pad) * 4);
+    const size_t ntiles = (size_t)cfg.tiles_a * cfg.tiles_b;
+    if (thin) {
+        L.cnt = take(N);
+        L.plist = take(N * 4);
+        L.tflag = take(ntiles * 4);
+        L.tlist = take(ntiles * 4);
+        L.bcounts = take(thin_blocks(N) * 4);
+        L.boffs = take(thin_blocks(N) * 4);
+        L.sched = take(rlk::SCHED_RING * 8);
+    }
+    L.ctr = take(C_COUNT * 8);
+    L.red = take(rlk::RED_BLOCKS * 8);
+    L.red_i = take(rlk::RED_BLOCKS * 8);
+    L.total = o;
+    return L;
+}
+
+rl_status validate_params(const rl_params* p, std::string* why) {
+    if (!p) { *why = "NULL params"; return RL_E_INVAL; }
+    if (p->height < 1 || p->width < 1) { *why = "image size must be >= 1"; return RL_E_INVAL; }
+    if ((int64_t)p->height * p->width > (int64_t)1 << 30) { *why = "image too large"; return RL_E_INVAL; }
+    if (p->boundary != RL_BC_REFLECT && p->boundary != RL_BC_REPLICATE) { *why = "boundary"; return RL_E_INVAL; }
+    if (p->thin.mode < RL_THIN_OFF || p->thin.mode > RL_THIN_REL) { *why = "thin mode"; return RL_E_INVAL; }
+    if (p->thin.mode != RL_THIN_OFF) {
+        if (!(p->thin.tau >= 0.f) || std::isinf(p->thin.tau)) { *why = "tau"; return RL_E_INVAL; }
+        if (p->thin.hysteresis < 1 || p->thin.hysteresis > 255) { *why = "hysteresis in [1, 255]"; return RL_E_INVAL; }
+        if (p->thin.reset_period < 0 || p->thin.compact_period < 0) { *why = "periods"; return RL_E_INVAL; }
+    }
+    return RL_OK;
+}
+
+}  // namespace
+
+struct rl_job {
+    rl_params p;
+    hipStream_t stream;
+    int H, W;
+    int64_t N;
+    Config cfg;
+    rl::CompiledPsf psf;
+    Layout L;
+    char* ws;
+    int64_t k;
+    bool list_valid;
+    bool live;
+    std::vector<DevSpan> h_conv, h_corr;
+    std::vector<float> h_conv_w, h_corr_w;
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rl_status dev_err(hipError_t e, const char* what) {
+    if (e == hipSuccess) return RL_OK;
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return RL_E_DEVICE;
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch(const char* name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                  size_t lds, hipStream_t s, Args... args) {
+    TimedLaunch tl;
+    bool timed = false;
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        timed = g_timing;
+    }
+    if (timed) {
+        (void)hipEventCreate(&tl.a);
+        (void)hipEventCreate(&tl.b);
+        (void)hipEventRecord(tl.a, s);
+    }
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    hipError_t e = hipGetLastError();
+    if (timed) {
+        (void)hipEventRecord(tl.b, s);
+        tl.name = name;
+        std::lock_guard<std::mutex> g(g_tmu);
+        g_timed.push_back(tl);
+    }
+    return e;
+}
+
+unsigned grid_for(int64_t n, int64_t per = 256, int64_t cap = 4096) {
+    int64_t g = (n + per - 1) / per;
+    return (unsigned)std::max<int64_t>(1, std::min(g, cap));
+}
+
+// ---- kernel instantiation tables --------------------------------------------------------
+using PhaseFn = void (*)(PhaseArgs);
+
+template <int O, int S, bool B>
+PhaseFn span_fn(int lmax) {
+    switch (lmax) {
+        case 1: return rlk::span_kernel<O, S, 1, kNW, B>;
+        case 2: return rlk::span_kernel<O, S, 2, kNW, B>;
+        case 4: return rlk::span_kernel<O, S, 4, kNW, B>;
+        case 8: return rlk::span_kernel<O, S, 8, kNW, B>;
+        case 16: return rlk::span_kernel<O, S, 16, kNW, B>;
+    }
+    return nullptr;
+}
+
+template <int O, bool B>
+PhaseFn span_fn_s(int S, int lmax) {
+    return S == 16 ? span_fn<O, 16, B>(lmax) : span_fn<O, 8, B>(lmax);
+}
+
+template <int O, bool B>
+PhaseFn slide_fn(int S) {
+    switch (S) {
+        case 8: return rlk::slide_kernel<O, 8, kNW, B>;
+        case 16: return rlk::slide_kernel<O, 16, kNW, B>;
+        case 32: return rlk::slide_kernel<O, 32, kNW, B>;
+    }
+    return nullptr;
+}
+
+PhaseFn phase_fn(const Config& c, bool phase_b) {
+    if (c.kind == KIND_SPAN) {
+        if (c.orient == rlk::ORIENT_ROWS)
+            return phase_b ? span_fn_s<rlk::ORIENT_ROWS, true>(c.S, c.lmax)
+                           : span_fn_s<rlk::ORIENT_ROWS, false>(c.S, c.lmax);
+        return phase_b ? span_fn_s<rlk::ORIENT_COLS, true>(c.S, c.lmax)
+                       : span_fn_s<rlk::ORIENT_COLS, false>(c.S, c.lmax);
+    }
+    if (c.orient == rlk::ORIENT_ROWS)
+        return phase_b ? slide_fn<rlk::ORIENT_ROWS, true>(c.S) : slide_fn<rlk::ORIENT_ROWS, false>(c.S);
+    return phase_b ? slide_fn<rlk::ORIENT_COLS, true>(c.S) : slide_fn<rlk::ORIENT_COLS, false>(c.S);
+}
+
+const char* phase_name(const Config& c, bool phase_b) {
+    if (c.kind == KIND_SPAN)
+        return phase_b ? (c.lmax == 1 ? "direct_corr_update" : "span_corr_update")
+                       : (c.lmax == 1 ? "direct_conv_ratio" : "span_conv_ratio");
+    return phase_b ? "slide_corr_update" : "slide_conv_ratio";
+}
+
+using ResFn = void (*)(ResidentArgs);
+ResFn resident_fn(int orient, int seg) {
+#define RL_RES(O)                                              \
+    switch (seg) {                                             \
+        case 2: return rlk::resident_kernel<O, 2>;             \
+        case 4: return rlk::resident_kernel<O, 4>;             \
+        case 8: return rlk::resident_kernel<O, 8>;             \
+        case 16: return rlk::resident_kernel<O, 16>;           \
+        case 32: return rlk::resident_kernel<O, 32>;           \
+    }
+    if (orient == rlk::ORIENT_ROWS) { RL_RES(rlk::ORIENT_ROWS) }
+    else { RL_RES(rlk::ORIENT_COLS) }
+#undef RL_RES
+    return nullptr;
+}
+
+PhaseArgs phase_args(rl_job* j, bool phase_b, bool thin, bool full) {
+    PhaseArgs a{};
+    const Config& c = j->cfg;
+    const rl::OpTable& t = phase_b ? c.corr : c.conv;
+    a.H = j->H;
+    a.W = j->W;
+    a.bc = j->p.boundary;
+    a.kahan = j->p.kahan;
+    a.src = phase_b ? j->at<float>(j->L.r) : j->at<float>(j->L.u);
+    a.f = j->at<float>(j->L.f);
+    a.r = j->at<float>(j->L.r);
+    a.u = j->at<float>(j->L.u);
+    a.spans = phase_b ? j->at<DevSpan>(j->L.corr_spans) : j->at<DevSpan>(j->L.conv_spans);
+    a.wts = phase_b ? j->at<float>(j->L.corr_w) : j->at<float>(j->L.conv_w);
+    a.n_spans = (int32_t)t.spans.size();
+    a.lane_min = t.lane_min;
+    a.lane_max = t.lane_max;
+    a.c_min = t.c_min;
+    a.c_max = t.c_max;
+    a.tiles_a = c.tiles_a;
+    a.tiles_b = c.tiles_b;
+    a.k = j->k;
+    if (thin) {
+        a.cnt = j->at<uint8_t>(j->L.cnt);
+        a.thin_mode = j->p.thin.mode;
+        a.hyst = j->p.thin.hysteresis;
+        a.tau = j->p.thin.tau;
+        a.full = full ? 1 : 0;
+        a.sched = j->at<int64_t>(j->L.sched);
+        a.active_total = j->at<int64_t>(j->L.ctr) + C_ACTIVE_TOTAL;
+        if (!full) {
+            a.tile_list = j->at<int32_t>(j->L.tlist);
+            a.tile_count = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
+        }
+    }
+    return a;
+}
+
+rl_status rebuild_lists(rl_job* j) {
+    rlk::ThinListArgs a{};
+    a.cnt = j->at<uint8_t>(j->L.cnt);
+    a.N = j->N;
+    a.W = j->W;
+    a.hyst = j->p.thin.hysteresis;
+    a.orient = j->cfg.orient;
+    a.tiles_a = j->cfg.tiles_a;
+    a.TA = j->cfg.TA;
+    a.TB = j->cfg.TB;
+    a.block_counts = j->at<int32_t>(j->L.bcounts);
+    a.block_offsets = j->at<int32_t>(j->L.boffs);
+    a.tflag = j->at<int32_t>(j->L.tflag);
+    a.plist = j->at<int32_t>(j->L.plist);
+    a.plist_len = j->at<int64_t>(j->L.ctr) + C_PLIST_LEN;
+    const int nb = (int)thin_blocks(j->N);
+    a.n_blocks = nb;
+    hipStream_t s = j->stream;
+    rl_status st;
+    if ((st = dev_err(launch("thin_count", rlk::thin_count_kernel, dim3(nb), dim3(256), 0, s, a), "thin_count"))) return st;
+    if ((st = dev_err(launch("thin_scan", rlk::scan_counts_kernel, dim3(1), dim3(1024), 0, s,
+                             (const int32_t*)a.block_counts, a.block_offsets, nb, a.plist_len), "thin_scan"))) return st;
+    if ((st = dev_err(launch("thin_scatter", rlk::thin_scatter_kernel, dim3(nb), dim3(256), 0, s, a), "thin_scatter"))) return st;
+    int ntiles = j->cfg.tiles_a * j->cfg.tiles_b;
+    if ((st = dev_err(launch("tile_compact", rlk::tile_compact_kernel, dim3(1), dim3(1024), 0, s,
+                             a.tflag, ntiles, j->at<int32_t>(j->L.tlist),
+                             j->at<int64_t>(j->L.ctr) + C_TLIST_LEN), "tile_compact"))) return st;
+    j->list_valid = true;
+    return RL_OK;
+}
+
+rl_status enqueue_iterations(rl_job* j, int32_t n) {
+    const Config& c = j->cfg;
+    hipStream_t s = j->stream;
+    if (c.kind == KIND_RESIDENT) {
+        if (n == 0) return RL_OK;
+        ResidentArgs a{};
+        a.H = j->H;
+        a.W = j->W;
+        a.bc = j->p.boundary;
+        a.kahan = j->p.kahan;
+        a.u = j->at<float>(j->L.u);
+        a.f = j->at<float>(j->L.f);
+        a.n_iter = n;
+        a.lines_per_wg = c.lines_per_wg;
+        a.wpl = c.wpl;
+        a.conv_c0 = j->psf.box_c0;
+        a.len = j->psf.box_len;
+        // adjoint window = mirror of the forward window
+        a.corr_c0 = -(j->psf.box_c0 + j->psf.box_len - 1);
+        a.w = j->psf.box_w;
+        a.halo = j->psf.box_len - 1;
+        a.line_words = c.line_words;
+        unsigned grid = (unsigned)((c.lines + c.lines_per_wg - 1) / c.lines_per_wg);
+        unsigned block = (unsigned)(c.lines_per_wg * 64 * c.wpl);
+        rl_status st = dev_err(launch("resident_box", resident_fn(c.orient, c.seg), dim3(grid),
+                                      dim3(block), c.lds_a, s, a), "resident_box");
+        if (st) return st;
+        j->k += n;
+        return RL_OK;
+    }
+    const bool thin = j->p.thin.mode != RL_THIN_OFF;
+    const int ntiles = c.tiles_a * c.tiles_b;
+    PhaseFn fa = phase_fn(c, false), fb = phase_fn(c, true);
+    const char* na = phase_name(c, false);
+    const char* nbn = phase_name(c, true);
+    for (int i = 0; i < n; ++i) {
+        bool full = true;
+        if (thin) {
+            full = is_full(j->k, j->p.thin.reset_period);
+            if (!full && (!j->list_valid ||
+                          is_rebuild(j->k, j->p.thin.reset_period, j->p.thin.compact_period))) {
+                rl_status st = rebuild_lists(j);
+                if (st) return st;
+            }
+            // zero the ring slot of the next iteration (phase B of this one adds to slot k)
+            int64_t* slot = j->at<int64_t>(j->L.sched) + ((j->k + 1) % rlk::SCHED_RING);
+            rl_status st = dev_err(launch("ring_zero", rlk::set_i64_kernel, dim3(1), dim3(1), 0, s,
+                                          slot, (int64_t)0), "ring_zero");
+            if (st) return st;
+        }
+        PhaseArgs aa = phase_args(j, false, thin, full);
+        PhaseArgs ab = phase_args(j, true, thin, full);
+        rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, aa), na);
+        if (st) return st;
+        st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, ab), nbn);
+        if (st) return st;
+        j->k += 1;
+    }
+    return RL_OK;
+}
+
+std::vector<DevSpan> to_dev(const rl::OpTable& t) {
+    std::vector<DevSpan> v(t.spans.size());
+    if (!t.spans.empty()) std::memcpy(v.data(), t.spans.data(), v.size() * sizeof(DevSpan));
+    if (v.empty()) v.resize(1);
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rl_status_str(rl_status s) {
+    switch (s) {
+        case RL_OK: return "RL_OK";
+        case RL_E_INVAL: return "RL_E_INVAL";
+        case RL_E_NOMEM: return "RL_E_NOMEM";
+        case RL_E_DEVICE: return "RL_E_DEVICE";
+        case RL_E_STATE: return "RL_E_STATE";
+        case RL_E_UNSUPPORTED: return "RL_E_UNSUPPORTED";
+    }
+    return "RL_E_UNKNOWN";
+}
+
+rl_status rl_workspace_bytes(const rl_params* p, size_t* bytes) {
+    std::string why;
+    if (!bytes) return RL_E_INVAL;
+    rl_status st = validate_params(p, &why);
+    if (st) return st;
+    rl::CompiledPsf c;
+    if (!rl::compile_psf(p->psf, p->psf_h, p->psf_w, &c, &why)) return RL_E_INVAL;
+    Config cfg;
+    st = choose_config(p, c, &cfg, &why);
+    if (st) return st;
+    *bytes = make_layout(p, cfg).total;
+    return RL_OK;
+}
+
+rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
+    std::string why;
+    if (!out || !ws) return RL_E_INVAL;
+    *out = nullptr;
+    rl_status st = validate_params(p, &why);
+    if (st) return st;
+    if (!p->f) return RL_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return RL_E_INVAL;
+    rl::CompiledPsf c;
+    if (!rl::compile_psf(p->psf, p->psf_h, p->psf_w, &c, &why)) return RL_E_INVAL;
+    rl_job* j = new (std::nothrow) rl_job();
+    if (!j) return RL_E_NOMEM;
+    j->p = *p;
+    j->p.psf = nullptr;
+    j->stream = reinterpret_cast<hipStream_t>(p->stream);
+    j->H = p->height;
+    j->W = p->width;
+    j->N = (int64_t)p->height * p->width;
+    j->psf = c;
+    j->k = 0;
+    j->list_valid = false;
+    j->live = true;
+    st = choose_config(p, c, &j->cfg, &why);
+    if (st) { delete j; return st; }
+    j->L = make_layout(p, j->cfg);
+    if (ws_bytes < j->L.total) { delete j; return RL_E_NOMEM; }
+    j->ws = static_cast<char*>(ws);
+    hipStream_t s = j->stream;
+    // compiled PSF tables -> workspace (host copies stay alive in the job)
+    j->h_conv = to_dev(j->cfg.conv);
+    j->h_corr = to_dev(j->cfg.corr);
+    j->h_conv_w = j->cfg.conv.w;
+    j->h_conv_w.resize(j->h_conv_w.size() + 16, 0.f);
+    j->h_corr_w = j->cfg.corr.w;
+    j->h_corr_w.resize(j->h_corr_w.size() + 16, 0.f);
+    hipError_t e;
+    e = hipMemcpyAsync(j->at<void>(j->L.conv_spans), j->h_conv.data(), j->h_conv.size() * sizeof(DevSpan), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_spans), j->h_corr.data(), j->h_corr.size() * sizeof(DevSpan), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.conv_w), j->h_conv_w.data(), j->h_conv_w.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_w), j->h_corr_w.data(), j->h_corr_w.size() * 4, hipMemcpyHostToDevice, s);
+    if ((st = dev_err(e, "upload PSF"))) { delete j; return st; }
+    const int64_t N = j->N;
+    unsigned g = grid_for(N);
+    if ((st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.f), p->f, N), "copy f"))) { delete j; return st; }
+    if ((st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.u), p->u0 ? p->u0 : p->f, N), "copy u0"))) { delete j; return st; }
+    if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(g), dim3(256), 0, s, j->at<uint32_t>(j->L.r), 0u, N), "zero r"))) { delete j; return st; }
+    if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(1), dim3(256), 0, s, j->at<uint32_t>(j->L.ctr), 0u, (int64_t)C_COUNT * 2), "zero ctr"))) { delete j; return st; }
+    if (p->thin.mode != RL_THIN_OFF) {
+        int64_t nt = (int64_t)j->cfg.tiles_a * j->cfg.tiles_b;
+        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(N / 4 + 1)), dim3(256), 0, s, j->at<uint32_t>(j->L.cnt), 0u, (N + 3) / 4), "zero cnt"))) { delete j; return st; }
+        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(nt)), dim3(256), 0, s, j->at<uint32_t>(j->L.tflag), 0u, nt), "zero tflag"))) { delete j; return st; }
+        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(rlk::SCHED_RING * 2)), dim3(256), 0, s, j->at<uint32_t>(j->L.sched), 0u, (int64_t)rlk::SCHED_RING * 2), "zero ring"))) { delete j; return st; }
+    }
+    if ((st = dev_err(launch("check_f", rlk::check_f_kernel, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s,
+                             (const float*)j->at<float>(j->L.f), N, reinterpret_cast<int32_t*>(j->at<int64_t>(j->L.ctr) + C_F_INVALID)), "check f"))) { delete j; return st; }
+    *out = j;
+    return RL_OK;
+}
+
+rl_status rl_iterate(rl_job* j, int32_t n_iter) {
+    if (!j) return RL_E_INVAL;
+    if (!j->live) return RL_E_STATE;
+    if (n_iter < 0) return RL_E_INVAL;
+    return enqueue_iterations(j, n_iter);
+}
+
+rl_status rl_result(rl_job* j, float* u_out, rl_stats* st) {
+    if (!j) return RL_E_INVAL;
+    if (!j->live) return RL_E_STATE;
+    hipStream_t s = j->stream;
+    rl_status rs;
+    if (u_out) {
+        if ((rs = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(grid_for(j->N)), dim3(256), 0, s, u_out, (const float*)j->at<float>(j->L.u), j->N), "copy u"))) return rs;
+    }
+    if (!st) return RL_OK;
+    int64_t* ctr = j->at<int64_t>(j->L.ctr);
+    const bool thin = j->p.thin.mode != RL_THIN_OFF;
+    if ((rs = dev_err(launch("reduce_sum", rlk::reduce_sum_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
+                             (const float*)j->at<float>(j->L.u), j->N, j->at<double>(j->L.red)), "reduce"))) return rs;
+    if (thin) {
+        if ((rs = dev_err(launch("count_active", rlk::count_active_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
+                                 (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N, (int)j->p.thin.hysteresis, j->at<int64_t>(j->L.red_i)), "count"))) return rs;
+    }
+    if ((rs = dev_err(launch("final_reduce", rlk::final_reduce_kernel, dim3(1), dim3(256), 0, s,
+                             (const double*)j->at<double>(j->L.red), thin ? (const int64_t*)j->at<int64_t>(j->L.red_i) : (const int64_t*)nullptr,
+                             reinterpret_cast<double*>(ctr + C_FLUX), thin ? ctr + C_ACTIVE_NOW : (int64_t*)nullptr), "final"))) return rs;
+    int64_t h[C_COUNT];
+    hipError_t e = hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((rs = dev_err(e, "read stats"))) return rs;
+    std::memset(st, 0, sizeof *st);
+    st->iters_done = j->k;
+    double flux;
+    std::memcpy(&flux, &h[C_FLUX], sizeof flux);
+    st->flux = flux;
+    if (thin) {
+        st->active_now = is_full(j->k, j->p.thin.reset_period) ? j->N : h[C_ACTIVE_NOW];
+        st->skipped_px_iters = j->k * j->N - h[C_ACTIVE_TOTAL];
+    } else {
+        st->active_now = j->N;
+        st->skipped_px_iters = 0;
+    }
+    st->path = j->cfg.path;
+    st->schedule = j->cfg.sched;
+    int32_t finv;
+    std::memcpy(&finv, &h[C_F_INVALID], sizeof finv);
+    st->f_invalid = finv ? 1 : 0;
+    return finv ? RL_E_INVAL : RL_OK;
+}
+
+rl_status rl_destroy(rl_job* j) {
+    if (!j) return RL_E_INVAL;
+    if (!j->live) return RL_E_STATE;
+    j->live = false;
+    delete j;
+    return RL_OK;
+}
+
+rl_status rl_batch_workspace_bytes(rl_job* const* jobs, int32_t n_jobs, size_t* bytes) {
+    (void)jobs;
+    (void)n_jobs;
+    if (!bytes) return RL_E_INVAL;
+    *bytes = 0;
+    return RL_E_UNSUPPORTED;
+}
+
+rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n_jobs, void* bws,
+                           size_t bws_bytes, void* stream) {
+    (void)jobs; (void)n_iter; (void)n_jobs; (void)bws; (void)bws_bytes; (void)stream;
+    return RL_E_UNSUPPORTED;
+}
+
+rl_status rl_get_state(rl_job* j, float* u, float* r, uint8_t* cnt, int64_t* k_out) {
+    if (!j) return RL_E_INVAL;
+    if (!j->live) return RL_E_STATE;
+    hipStream_t s = j->stream;
+    unsigned g = grid_for(j->N);
+    rl_status st;
+    if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, u, (const float*)j->at<float>(j->L.u), j->N), "get u"))) return st;
+    if (r && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, r, (const float*)j->at<float>(j->L.r), j->N), "get r"))) return st;
+    if (cnt) {
+        if (j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
+        if ((st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, cnt, (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N), "get cnt"))) return st;
+    }
+    if (k_out) *k_out = j->k;
+    return RL_OK;
+}
+
+rl_status rl_set_state(rl_job* j, const float* u, const float* r, const uint8_t* cnt, int64_t k) {
+    if (!j) return RL_E_INVAL;
+    if (!j->live) return RL_E_STATE;
+    if (k < 0) return RL_E_INVAL;
+    if (cnt && j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
+    hipStream_t s = j->stream;
+    unsigned g = grid_for(j->N);
+    rl_status st;
+    if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.u), u, j->N), "set u"))) return st;
+    if (r && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.r), r, j->N), "set r"))) return st;
+    if (cnt && (st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, j->at<uint8_t>(j->L.cnt), cnt, j->N), "set cnt"))) return st;
+    j->k = k;
+    j->list_valid = false;
+    if (j->p.thin.mode != RL_THIN_OFF) {
+        int64_t* slot = j->at<int64_t>(j->L.sched) + (k % rlk::SCHED_RING);
+        if ((st = dev_err(launch("ring_zero", rlk::set_i64_kernel, dim3(1), dim3(1), 0, s, slot, (int64_t)0), "ring"))) return st;
+    }
+    return RL_OK;
+}
+
+rl_status rl_active_list(rl_job* j, int32_t* list_dev, int64_t cap, int64_t* n) {
+    if (!j || !n) return RL_E_INVAL;
+    if (!j->live || j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
+    hipStream_t s = j->stream;
+    int64_t len = 0;
+    hipError_t e = hipMemcpyAsync(&len, j->at<int64_t>(j->L.ctr) + C_PLIST_LEN, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    rl_status st = dev_err(e, "list len");
+    if (st) return st;
+    *n = j->list_valid ? len : -1;
+    if (list_dev && len > 0 && j->list_valid) {
+        if (cap < len) return RL_E_NOMEM;
+        e = hipMemcpyAsync(list_dev, j->at<int32_t>(j->L.plist), (size_t)len * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if ((st = dev_err(e, "list copy"))) return st;
+    }
+    return RL_OK;
+}
+
+rl_status rl_thin_schedule(rl_job* j, int64_t* out, int32_t cap, int32_t* n) {
+    if (!j || !n) return RL_E_INVAL;
+    if (!j->live || j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
+    std::vector<int64_t> ring(rlk::SCHED_RING);
+    hipError_t e = hipMemcpyAsync(ring.data(), j->at<int64_t>(j->L.sched), ring.size() * 8, hipMemcpyDeviceToHost, j->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(j->stream);
+    rl_status st = dev_err(e, "schedule");
+    if (st) return st;
+    int64_t cnt = std::min<int64_t>(std::min<int64_t>(j->k, cap), rlk::SCHED_RING);
+    for (int64_t i = 0; i < cnt; ++i) {
+        int64_t kk = j->k - cnt + i;
+        if (out) out[i] = ring[kk % rlk::SCHED_RING];
+    }
+    *n = (int32_t)cnt;
+    return RL_OK;
+}
+
+rl_status rl_psf_runs(const float* psf, int32_t psf_h, int32_t psf_w, int32_t* runs, float* w,
+                      int32_t cap, int32_t* n_runs, int32_t* cls) {
+    std::string why;
+    rl::CompiledPsf c;
+    if (!rl::compile_psf(psf, psf_h, psf_w, &c, &why)) return RL_E_INVAL;
+    if (n_runs) *n_runs = (int32_t)c.runs.size();
+    if (cls) *cls = c.auto_path;
+    if ((int64_t)c.runs.size() > cap) return RL_E_NOMEM;
+    for (size_t i = 0; i < c.runs.size(); ++i) {
+        if (runs) {
+            runs[3 * i + 0] = c.runs[i].dy;
+            runs[3 * i + 1] = c.runs[i].x0;
+            runs[3 * i + 2] = c.runs[i].x1;
+        }
+        if (w) w[i] = c.runs[i].w;
+    }
+    return RL_OK;
+}
+
+rl_status rl_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_timing = on != 0;
+    return RL_OK;
+}
+
+rl_status rl_timing_read(const char* name, int64_t* launches, double* total_ms) {
+    if (!name || !launches || !total_ms) return RL_E_INVAL;
+    std::lock_guard<std::mutex> g(g_tmu);
+    int64_t n = 0;
+    double tot = 0;
+    for (TimedLaunch& t : g_timed) {
+        if (t.name != name) continue;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return dev_err(e, "timing");
+        float ms = 0;
+        e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess) return dev_err(e, "timing");
+        ++n;
+        tot += ms;
+    }
+    *launches = n;
+    *total_ms = tot;
+    return RL_OK;
+}
+
+rl_status rl_timing_reset(void) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    for (TimedLaunch& t : g_timed) {
+        (void)hipEventSynchronize(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_timed.clear();
+    return RL_OK;
+}
+
+rl_status rl_job_describe(rl_job* j, rl_job_info* info) {
+    if (!j || !info) return RL_E_INVAL;
+    if (!j->live) return RL_E_STATE;
+    std::memset(info, 0, sizeof *info);
+    const Config& c = j->cfg;
+    info->path = c.path;
+    info->schedule = c.sched;
+    if (c.kind == KIND_RESIDENT) {
+        info->tile_h = c.orient == rlk::ORIENT_ROWS ? c.lines_per_wg : c.line_n;
+        info->tile_w = c.orient == rlk::ORIENT_ROWS ? c.line_n : c.lines_per_wg;
+        info->strip = c.seg;
+        info->n_spans = 1;
+        info->n_taps = j->psf.n_taps;
+    } else {
+        info->tile_h = c.orient == rlk::ORIENT_ROWS ? c.TA : c.TB;
+        info->tile_w = c.orient == rlk::ORIENT_ROWS ? c.TB : c.TA;
+        info->strip = c.S;
+        info->n_spans = (int32_t)c.conv.spans.size();
+        info->n_taps = j->psf.n_taps;
+        info->lmax = c.kind == KIND_SPAN ? c.lmax : 0;
+        info->halo_y0 = c.orient == rlk::ORIENT_ROWS ? c.conv.lane_min : c.conv.c_min;
+        info->halo_y1 = c.orient == rlk::ORIENT_ROWS ? c.conv.lane_max : c.conv.c_max;
+        info->halo_x0 = c.orient == rlk::ORIENT_ROWS ? c.conv.c_min : c.conv.lane_min;
+        info->halo_x1 = c.orient == rlk::ORIENT_ROWS ? c.conv.c_max : c.conv.lane_max;
+    }
+    info->ws_bytes = (int64_t)j->L.total;
+    return RL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,815 @@
+// HIP kernels for CDNA4 (gfx950): the Richardson-Lucy hot path.
+//
+//   phase A   v = u^k * h  (forward convolution), r = f / v            (Section 2, eq. 3)
+//   phase B   c = h^* * r  (adjoint correlation), u^{k+1} = u^k . c   (Section 2, eq. 3)
+//   thinning  pixels with a converged counter are skipped; every R-th step is full,
+//             and the active set is recompacted into a list           (Section 4, eq. 4-5)
+//
+// Operators are evaluated in "correlation form": out(a, b) = sum over spans of
+// sum_t w[t] * src(a + lane_off, b + c0 + t).  Axis a is the lane axis (one wavefront lane
+// per image line), axis b is the strip axis (each lane produces S consecutive outputs).
+// ORIENT_ROWS: a = row, b = column.  ORIENT_COLS: a = column, b = row.
+// The LDS tile is always stored row-major (image rows), with an odd pitch so that lanes
+// reading different rows of the same column hit different banks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rlk {
+
+constexpr int ORIENT_ROWS = 0;
+constexpr int ORIENT_COLS = 1;
+constexpr int BC_REFLECT = 0;
+constexpr int BC_REPLICATE = 1;
+constexpr int THIN_OFF = 0;
+constexpr int THIN_ABS = 1;
+constexpr int THIN_REL = 2;
+constexpr int SCHED_RING = 4096;  // per-iteration active-count ring
+
+// device copy of rl::Span (same layout)
+struct DevSpan {
+    int32_t lane_off, c0, len, woff;
+    float w0;
+    int32_t uniform, row_end, pad;
+};
+
+// The PSF tables do not change while a kernel runs; reading them through the constant
+// address space lets the compiler use scalar loads (one per wavefront, through the scalar
+// cache) instead of per-lane vector loads with a full memory round trip per span.
+typedef const __attribute__((address_space(4))) DevSpan* ConstSpanPtr;
+typedef const __attribute__((address_space(4))) float* ConstFloatPtr;
+__device__ __forceinline__ ConstSpanPtr as_const(const DevSpan* p) { return (ConstSpanPtr)p; }
+__device__ __forceinline__ ConstFloatPtr as_const(const float* p) { return (ConstFloatPtr)p; }
+__device__ __forceinline__ DevSpan load_span(ConstSpanPtr t, int i) {
+    DevSpan s;
+    s.lane_off = t[i].lane_off;
+    s.c0 = t[i].c0;
+    s.len = t[i].len;
+    s.woff = t[i].woff;
+    s.w0 = t[i].w0;
+    s.uniform = t[i].uniform;
+    s.row_end = t[i].row_end;
+    s.pad = 0;
+    return s;
+}
+
+// Boundary fold of index i into [0, n) (Section 2, "Boundary treatment").
+__device__ __forceinline__ int fold_idx(int i, int n, int bc) {
+    if ((unsigned)i < (unsigned)n) return i;
+    if (bc == BC_REPLICATE) return i < 0 ? 0 : n - 1;
+    int m = 2 * n;
+    int p = i % m;
+    if (p < 0) p += m;
+    return p < n ? p : m - 1 - p;
+}
+
+// Kahan-compensated accumulation: s + x with running compensation c.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// The float32 convergence test of thinned RL (Section 4), one rounded op per step.
+__device__ __forceinline__ bool thin_below(float a, float b, int mode, float tau) {
+    if (!(tau > 0.f)) return false;
+    if (b == 0.f && a == 0.f) return true;
+    float d = __fsub_rn(a, b);
+    float ad = fabsf(d);
+    float t = (mode == THIN_REL) ? __fmul_rn(tau, b) : tau;
+    return ad < t;
+}
+
+// r = f / v for v > 0, else 0 (IEEE-rounded division).
+__device__ __forceinline__ float rl_ratio(float f, float v) {
+    return v > 0.f ? __fdiv_rn(f, v) : 0.f;
+}
+
+struct PhaseArgs {
+    int32_t H, W, bc, kahan;
+    const float* src;     // u^k (phase A) or r (phase B)
+    const float* f;       // phase A
+    float* r;             // phase A output
+    float* u;             // phase B in/out
+    uint8_t* cnt;         // thinning counters (NULL when off)
+    const DevSpan* spans; // operator table
+    const float* wts;     // operator weights (padded with zeros)
+    int32_t n_spans;
+    int32_t lane_min, lane_max, c_min, c_max;
+    int32_t tiles_a, tiles_b;      // tile grid (lane axis, strip axis)
+    const int32_t* tile_list;      // thinned non-full step: list of tile ids, else NULL
+    const int64_t* tile_count;     // its length (device)
+    int32_t thin_mode, hyst, full; // thinning
+    float tau;
+    int64_t* sched;                // active-count ring (thinning)
+    int64_t* active_total;         // running sum of |A_k|
+    int64_t k;                     // iteration index
+};
+
+// Map a workgroup index to a tile so that each XCD (workgroups are dispatched to the 8
+// XCDs round-robin) gets one contiguous range of tiles: neighbouring tiles share halo
+// rows/columns, which then stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    int xcd = b & 7, idx = b >> 3;
+    int base = n >> 3, rem = n & 7;
+    int start = xcd * base + (xcd < rem ? xcd : rem);
+    return start + idx;
+}
+
+// Resolve this workgroup's tile (a0, b0); returns false if it has none.
+__device__ __forceinline__ bool resolve_tile(const PhaseArgs& p, int TA, int TB, int& a0,
+                                             int& b0) {
+    int n;
+    if (p.tile_list) n = (int)*p.tile_count;
+    else n = p.tiles_a * p.tiles_b;
+    int nb = gridDim.x;
+    if ((int)blockIdx.x >= nb) return false;
+    // the remap is only a permutation when every block has a tile; otherwise go linear
+    int slot = (n == nb) ? xcd_tile(blockIdx.x, nb) : (int)blockIdx.x;
+    if (slot >= n) return false;
+    int t = p.tile_list ? p.tile_list[slot] : slot;
+    a0 = (t % p.tiles_a) * TA;
+    b0 = (t / p.tiles_a) * TB;
+    return true;
+}
+
+// Cooperative load of the source tile (with halo and boundary fold) into LDS.
+// LDS holds rows [ly0, ly0 + ny) x cols [lx0, lx0 + nx) of the folded image, row-major
+// with the given pitch.  Each wavefront takes whole rows with its lanes along the columns
+// (coalesced), and every (row, 64-column chunk) is one global-to-LDS DMA load
+// (global_load_lds_dword: no VGPRs, no dependence on earlier loads), so the whole tile is
+// in flight at once.  Lanes past the row end are masked off, so the DMA never writes
+// outside the row.  The caller waits (lds_dma_wait) and synchronises before reading.
+constexpr int MAXC = 5;
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void load_tile(float* lds, const float* __restrict__ src, int H,
+                                          int W, int bc, int ly0, int lx0, int ny, int nx,
+                                          int pitch) {
+    const int nwv = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int gx[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        int col = lane + 64 * c;
+        gx[c] = col < nx ? fold_idx(lx0 + col, W, bc) : 0;
+    }
+    const int nch = (nx + 63) >> 6;
+    for (int row = wv; row < ny; row += nwv) {
+        const float* srow = src + (size_t)fold_idx(ly0 + row, H, bc) * W;
+        float* drow = lds + row * pitch;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            if (c < nch) {
+                if (lane + 64 * c < nx)
+                    __builtin_amdgcn_global_load_lds((const void*)(srow + gx[c]),
+                                                     (lds_void*)(drow + 64 * c), 4, 0, 0);
+            }
+        }
+    }
+}
+
+// Wait for this wavefront's outstanding global loads, including LDS DMA.
+__device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Epilogue inputs of one output at linear position q: f (phase A) or u^k (phase B), and
+// the convergence counter in thinned mode.  Gathered for all outputs of a lane before any
+// is applied, so the global loads overlap.
+struct EpiIn {
+    float x;
+    uint8_t c8;
+};
+
+template <bool PHASE_B>
+__device__ __forceinline__ EpiIn epi_load(const PhaseArgs& p, size_t q) {
+    EpiIn e;
+    e.x = PHASE_B ? p.u[q] : p.f[q];
+    e.c8 = p.cnt ? p.cnt[q] : (uint8_t)0;
+    return e;
+}
+
+// Apply the epilogue: phase A writes r = f / v; phase B writes u^{k+1} = u^k . c and, in
+// thinned mode, the counter.  Inactive pixels (thinned, non-full step) are left alone.
+// Returns 1 if the pixel was active.
+template <bool PHASE_B>
+__device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, float val) {
+    if (p.cnt && !(p.full || (int)e.c8 < p.hyst)) return 0;
+    if (!PHASE_B) {
+        p.r[q] = rl_ratio(e.x, val);
+    } else {
+        float un = __fmul_rn(e.x, val);
+        p.u[q] = un;
+        if (p.cnt && p.thin_mode != THIN_OFF) {
+            bool below = thin_below(un, e.x, p.thin_mode, p.tau);
+            p.cnt[q] = below ? (uint8_t)(e.c8 < 255 ? e.c8 + 1 : 255) : (uint8_t)0;
+        }
+    }
+    return 1;
+}
+
+// Per-wave sum of an int and one atomic add (thinned mode active counts).
+__device__ __forceinline__ void add_active(const PhaseArgs& p, int n_active) {
+    if (!p.cnt) return;
+    for (int off = 32; off > 0; off >>= 1) n_active += __shfl_xor(n_active, off);
+    if ((threadIdx.x & 63) == 0 && n_active) {
+        atomicAdd((unsigned long long*)&p.sched[p.k % SCHED_RING],
+                  (unsigned long long)n_active);
+        atomicAdd((unsigned long long*)p.active_total, (unsigned long long)n_active);
+    }
+}
+
+// Common tile set-up.  TA = 64 lanes, TB = NW * S strip positions.
+template <int ORIENT>
+struct TileGeom {
+    int a0, b0, ly0, lx0, ny, nx, pitch;
+    // LDS index of the element at tile-relative (a, b) (a already includes -lane_min,
+    // b already includes -c_min).
+    __device__ __forceinline__ int idx(int a, int b) const {
+        return ORIENT == ORIENT_ROWS ? a * pitch + b : b * pitch + a;
+    }
+};
+
+template <int ORIENT>
+__device__ __forceinline__ TileGeom<ORIENT> make_geom(const PhaseArgs& p, int a0, int b0,
+                                                       int TA, int TB, int extra) {
+    TileGeom<ORIENT> g;
+    g.a0 = a0;
+    g.b0 = b0;
+    int na = TA + p.lane_max - p.lane_min;
+    int nb = TB + p.c_max - p.c_min + extra;
+    if (ORIENT == ORIENT_ROWS) {
+        g.ly0 = a0 + p.lane_min;
+        g.lx0 = b0 + p.c_min;
+        g.ny = na;
+        g.nx = nb;
+    } else {
+        g.ly0 = b0 + p.c_min;
+        g.lx0 = a0 + p.lane_min;
+        g.ny = nb;
+        g.nx = na;
+    }
+    g.pitch = g.nx | 1;
+    return g;
+}
+
+// Epilogue inputs of the outputs a lane finishes: for ORIENT_COLS the lane's own strip
+// (lanes are consecutive columns, so every access is coalesced), for ORIENT_ROWS the
+// elements the lane handles after the LDS transpose.  Loaded at kernel entry so that they
+// travel together with the tile.
+template <int ORIENT, int S, int NW>
+struct EpiPlan {
+    static constexpr int TB = NW * S;
+    static constexpr int PER = ORIENT == ORIENT_COLS ? S : (64 * TB) / (NW * 64);
+    EpiIn in[PER];
+};
+
+template <int ORIENT, int S, int NW>
+__device__ __forceinline__ void epi_pos(int i, int a0, int b0, int& y, int& x) {
+    constexpr int TB = NW * S;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (ORIENT == ORIENT_COLS) {
+        x = a0 + lane;
+        y = b0 + wv * S + i;
+    } else {
+        int e = threadIdx.x + i * NW * 64;
+        int row = e / TB, col = e % TB;
+        y = a0 + row;
+        x = b0 + col;
+    }
+}
+
+template <int ORIENT, int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void epi_prefetch(const PhaseArgs& p, int a0, int b0,
+                                             EpiPlan<ORIENT, S, NW>& plan) {
+#pragma unroll
+    for (int i = 0; i < EpiPlan<ORIENT, S, NW>::PER; ++i) {
+        int y, x;
+        epi_pos<ORIENT, S, NW>(i, a0, b0, y, x);
+        if (x < p.W && y < p.H) plan.in[i] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+    }
+}
+
+template <int ORIENT, int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, int a0, int b0,
+                                              const float (&out)[S],
+                                              const EpiPlan<ORIENT, S, NW>& plan) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int n_active = 0;
+    if (ORIENT == ORIENT_COLS) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            int y, x;
+            epi_pos<ORIENT, S, NW>(s, a0, b0, y, x);
+            if (x < p.W && y < p.H)
+                n_active += epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[s], out[s]);
+        }
+    } else {
+        constexpr int TB = NW * S;
+        constexpr int SP = TB + 1;
+        __syncthreads();  // everyone is done reading the source tile
+#pragma unroll
+        for (int s = 0; s < S; ++s) lds[lane * SP + wv * S + s] = out[s];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EpiPlan<ORIENT, S, NW>::PER; ++i) {
+            int e = threadIdx.x + i * NW * 64;
+            int row = e / TB, col = e % TB;
+            int y, x;
+            epi_pos<ORIENT, S, NW>(i, a0, b0, y, x);
+            if (y < p.H && x < p.W)
+                n_active += epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[i],
+                                               lds[row * SP + col]);
+        }
+    }
+    if (PHASE_B) add_active(p, n_active);
+}
+
+// ---------------------------------------------------------------------------------------
+// Span kernel: every PSF line is cut into pieces of at most LMAX taps (any weights).  Each
+// lane keeps a register window of S + LMAX - 1 source values per piece and forms S outputs
+// from it (register blocking: one LDS read per output per piece instead of one per tap).
+// Partial sums are per PSF line in float32; lines are combined with Kahan compensation
+// (kahan = 1) or plainly.  LMAX = 1 with the per-tap table is the DIRECT path.
+// ---------------------------------------------------------------------------------------
+template <int ORIENT, int S, int LMAX, int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void span_kernel(PhaseArgs p) {
+    extern __shared__ float lds[];
+    constexpr int TA = 64, TB = NW * S;
+    int a0, b0;
+    if (!resolve_tile(p, TA, TB, a0, b0)) return;
+    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, LMAX - 1);
+    EpiPlan<ORIENT, S, NW> plan;
+    epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
+    load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
+    lds_dma_wait();
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int la = lane - p.lane_min;
+    const int lb = wv * S - p.c_min;
+    float acc[S], comp[S], part[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) { acc[s] = 0.f; comp[s] = 0.f; part[s] = 0.f; }
+    const bool kahan = p.kahan != 0;
+
+    const ConstSpanPtr spans = as_const(p.spans);
+    const ConstFloatPtr wts = as_const(p.wts);
+    for (int i = 0; i < p.n_spans; ++i) {
+        const DevSpan sp = load_span(spans, i);
+        const ConstFloatPtr wp = wts + sp.woff;
+        float wv_[LMAX];
+#pragma unroll
+        for (int t = 0; t < LMAX; ++t) wv_[t] = (t < sp.len) ? wp[t] : 0.f;
+        const int ia = la + sp.lane_off, ib = lb + sp.c0;
+        float win[S + LMAX - 1];
+#pragma unroll
+        for (int q = 0; q < S + LMAX - 1; ++q) win[q] = lds[g.idx(ia, ib + q)];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            float a = part[s];
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t) a = fmaf(wv_[t], win[s + t], a);
+            part[s] = a;
+        }
+        if (sp.row_end) {
+            if (kahan) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) { kahan_add(acc[s], comp[s], part[s]); part[s] = 0.f; }
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; ++s) { acc[s] += part[s]; part[s] = 0.f; }
+            }
+        }
+    }
+    write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, acc, plan);
+}
+
+// ---------------------------------------------------------------------------------------
+// Sliding kernel (generic box filter): every span is a run of equal weights.  Moving the
+// output one step along the strip adds the entering tap and removes the leaving tap of each
+// run, 2 operations per run per output.  The first output of the strip is seeded by the
+// full sum (per-run partials combined with Kahan); the per-step changes are combined in a
+// Kahan-compensated running sum (kahan = 1) or a plain one.
+// ---------------------------------------------------------------------------------------
+template <int ORIENT, int S, int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void slide_kernel(PhaseArgs p) {
+    extern __shared__ float lds[];
+    constexpr int TA = 64, TB = NW * S;
+    int a0, b0;
+    if (!resolve_tile(p, TA, TB, a0, b0)) return;
+    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
+    EpiPlan<ORIENT, S, NW> plan;
+    epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
+    load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
+    lds_dma_wait();
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int la = lane - p.lane_min;
+    const int lb = wv * S - p.c_min;
+    const bool kahan = p.kahan != 0;
+    float seed = 0.f, seed_c = 0.f;
+    float d[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) d[s] = 0.f;
+
+    const ConstSpanPtr spans = as_const(p.spans);
+    for (int i = 0; i < p.n_spans; ++i) {
+        const DevSpan sp = load_span(spans, i);
+        const float w = sp.w0;
+        const int ia = la + sp.lane_off, ib = lb + sp.c0;
+        const int len = sp.len;
+        // seed: the run's full sum at the strip's first output, four independent chains
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+        int q = 0;
+        for (; q + 4 <= len; q += 4) {
+            p0 += lds[g.idx(ia, ib + q)];
+            p1 += lds[g.idx(ia, ib + q + 1)];
+            p2 += lds[g.idx(ia, ib + q + 2)];
+            p3 += lds[g.idx(ia, ib + q + 3)];
+        }
+        for (; q < len; ++q) p0 += lds[g.idx(ia, ib + q)];
+        const float part = (p0 + p1) + (p2 + p3);
+        if (kahan) kahan_add(seed, seed_c, w * part);
+        else seed = fmaf(w, part, seed);
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            float in = lds[g.idx(ia, ib + s + len - 1)];
+            float outv = lds[g.idx(ia, ib + s - 1)];
+            d[s] = fmaf(w, in - outv, d[s]);
+        }
+    }
+    float out[S];
+    float run = seed, c = seed_c;
+    out[0] = run;
+#pragma unroll
+    for (int s = 1; s < S; ++s) {
+        if (kahan) kahan_add(run, c, d[s]);
+        else run += d[s];
+        out[s] = run;
+    }
+    write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, out, plan);
+}
+
+// ---------------------------------------------------------------------------------------
+// Resident line solver for axis-aligned box PSFs (1 x L or L x 1).  Such a PSF couples
+// pixels only along one image line, so every line is an independent 1-D RL problem.  A
+// workgroup keeps LINES whole lines of u and r in LDS (f in registers) and runs all
+// iterations of the call on chip; HBM is touched once at the start and once at the end.
+// One or more wavefronts per line; each lane owns SEG consecutive pixels and evaluates
+// the box by a sliding window (seeded per segment, Kahan-compensated when kahan = 1).
+// Each LDS line carries a halo of HALO = L - 1 positions on both sides (plus SEG on the
+// right for the last segment's unused tail) holding the boundary continuation: whoever
+// writes a pixel also writes its mirror images, so no read needs a fold.  This needs
+// HALO <= line length (a single reflection); deeper folds use the tiled kernels.
+// LDS index of line position pos (pos >= -HALO): pos + HALO plus one pad word per SEG
+// positions, which keeps the lanes of a wavefront on distinct banks.
+// ---------------------------------------------------------------------------------------
+struct ResidentArgs {
+    int32_t H, W, bc, kahan;
+    float* u;          // in/out (global)
+    const float* f;
+    int32_t n_iter;
+    int32_t lines_per_wg, wpl;      // lines per workgroup, wavefronts per line
+    int32_t conv_c0, corr_c0, len;  // window [c0, c0 + len) for conv and corr
+    int32_t halo;                   // L - 1
+    int32_t line_words;             // LDS words per line and plane
+    float w;                        // box weight
+};
+
+template <int SEG>
+__device__ __forceinline__ int line_idx(int pos, int halo) {
+    const unsigned e = (unsigned)(pos + halo);
+    return (int)(e + e / SEG);
+}
+
+// Write v at line position pos in [0, n) and at every halo position that continues it.
+template <int SEG>
+__device__ __forceinline__ void line_store(float* line, int pos, int n, int halo, int bc,
+                                           float v) {
+    line[line_idx<SEG>(pos, halo)] = v;
+    if (bc == BC_REFLECT) {
+        if (pos < halo) line[line_idx<SEG>(-1 - pos, halo)] = v;
+        if (pos >= n - halo) line[line_idx<SEG>(2 * n - 1 - pos, halo)] = v;
+    } else {
+        if (pos == 0)
+            for (int m = 1; m <= halo; ++m) line[line_idx<SEG>(-m, halo)] = v;
+        if (pos == n - 1)
+            for (int m = 0; m < halo; ++m) line[line_idx<SEG>(n + m, halo)] = v;
+    }
+}
+
+// Window sums out[q] = sum_{t < len} line[p0 + q + c0 + t], q = 0..SEG-1 (halo-extended
+// line, no folds), by a sliding window seeded at q = 0.  All LDS reads are issued before
+// the dependent running sum.
+template <int SEG>
+__device__ __forceinline__ void box_segment(const float* line, int halo, int p0, int c0,
+                                            int len, bool kahan, float (&out)[SEG]) {
+    const int lo = p0 + c0;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int q = 0;
+#pragma unroll 1
+    for (; q + 4 <= len; q += 4) {
+        s0 += line[line_idx<SEG>(lo + q, halo)];
+        s1 += line[line_idx<SEG>(lo + q + 1, halo)];
+        s2 += line[line_idx<SEG>(lo + q + 2, halo)];
+        s3 += line[line_idx<SEG>(lo + q + 3, halo)];
+    }
+    for (; q < len; ++q) s0 += line[line_idx<SEG>(lo + q, halo)];
+    float din[SEG], dout[SEG];
+#pragma unroll
+    for (int q2 = 1; q2 < SEG; ++q2) {
+        din[q2] = line[line_idx<SEG>(lo + q2 + len - 1, halo)];
+        dout[q2] = line[line_idx<SEG>(lo + q2 - 1, halo)];
+    }
+    float run = (s0 + s1) + (s2 + s3), c = 0.f;
+    out[0] = run;
+#pragma unroll
+    for (int q2 = 1; q2 < SEG; ++q2) {
+        float d = din[q2] - dout[q2];
+        if (kahan) kahan_add(run, c, d);
+        else run += d;
+        out[q2] = run;
+    }
+}
+
+template <int ORIENT, int SEG>
+__global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
+    extern __shared__ float lds[];
+    const int n = (ORIENT == ORIENT_ROWS) ? a.W : a.H;       // line length
+    const int m = (ORIENT == ORIENT_ROWS) ? a.H : a.W;       // number of lines
+    const int tpl = 64 * a.wpl;                               // threads per line
+    const int j = threadIdx.x / tpl;                          // line within the workgroup
+    const int t = threadIdx.x % tpl;                          // segment within the line
+    const int line = blockIdx.x * a.lines_per_wg + j;
+    const bool live = (j < a.lines_per_wg) && (line < m);
+    const int halo = a.halo;
+    float* ul = lds + (size_t)j * 2 * a.line_words;
+    float* rl = ul + a.line_words;
+    const int p0 = t * SEG;
+    const bool work = live && p0 < n;
+
+    auto gidx = [&](int pos) -> size_t {
+        return ORIENT == ORIENT_ROWS ? (size_t)line * a.W + pos : (size_t)pos * a.W + line;
+    };
+
+    // zero both planes once (the last segment's tail reads past the right halo)
+    for (int e = threadIdx.x; e < a.lines_per_wg * 2 * a.line_words; e += blockDim.x) lds[e] = 0.f;
+    __syncthreads();
+    float fr[SEG];
+    if (live) {
+        float uv[SEG];
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) {
+            int pos = p0 + q;
+            fr[q] = pos < n ? a.f[gidx(pos)] : 0.f;
+            uv[q] = pos < n ? a.u[gidx(pos)] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < SEG; ++q)
+            if (p0 + q < n) line_store<SEG>(ul, p0 + q, n, halo, a.bc, uv[q]);
+    }
+    __syncthreads();
+    const bool kahan = a.kahan != 0;
+
+    for (int it = 0; it < a.n_iter; ++it) {
+        if (work) {  // forward box + ratio
+            float v[SEG];
+            box_segment<SEG>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
+#pragma unroll
+            for (int q = 0; q < SEG; ++q)
+                if (p0 + q < n) line_store<SEG>(rl, p0 + q, n, halo, a.bc, rl_ratio(fr[q], a.w * v[q]));
+        }
+        __syncthreads();
+        if (work) {  // adjoint box + multiplicative update
+            float c[SEG];
+            box_segment<SEG>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
+#pragma unroll
+            for (int q = 0; q < SEG; ++q) {
+                int pos = p0 + q;
+                if (pos < n) {
+                    float un = __fmul_rn(ul[line_idx<SEG>(pos, halo)], a.w * c[q]);
+                    line_store<SEG>(ul, pos, n, halo, a.bc, un);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) {
+            int pos = p0 + q;
+            if (pos < n) a.u[gidx(pos)] = ul[line_idx<SEG>(pos, halo)];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Thinning bookkeeping.
+// ---------------------------------------------------------------------------------------
+// Per block of 256 pixels: number of active pixels (cnt < hyst), via wavefront ballots.
+// Also flags the tile of every active pixel (all writers store 1).
+struct ThinListArgs {
+    const uint8_t* cnt;
+    int64_t N;
+    int32_t W, hyst, orient, tiles_a, TA, TB;
+    int32_t* block_counts;
+    int32_t* block_offsets;
+    int32_t* tflag;
+    int32_t* plist;
+    int64_t* plist_len;
+    int32_t n_blocks;
+};
+
+__device__ __forceinline__ int tile_of(const ThinListArgs& a, int64_t p) {
+    int y = (int)(p / a.W), x = (int)(p - (int64_t)y * a.W);
+    int ta, tb;
+    if (a.orient == ORIENT_ROWS) { ta = y / a.TA; tb = x / a.TB; }
+    else { ta = x / a.TA; tb = y / a.TB; }
+    return tb * a.tiles_a + ta;
+}
+
+__global__ __launch_bounds__(256) void thin_count_kernel(ThinListArgs a) {
+    __shared__ int wsum[4];
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool act = (p < a.N) && ((int)a.cnt[p] < a.hyst);
+    if (act) a.tflag[tile_of(a, p)] = 1;
+    unsigned long long m = __ballot(act);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) a.block_counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Exclusive scan of the block counts by one workgroup of 1024 threads (fixed order).
+__global__ __launch_bounds__(1024) void scan_counts_kernel(const int32_t* counts,
+                                                           int32_t* offsets, int n,
+                                                           int64_t* total) {
+    __shared__ int64_t part[1024];
+    const int per = (n + 1023) / 1024;
+    const int lo = threadIdx.x * per;
+    int64_t s = 0;
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) s += counts[lo + i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over 1024 partials
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) {
+            offsets[lo + i] = (int32_t)run;
+            run += counts[lo + i];
+        }
+    if (threadIdx.x == 1023) *total = part[1023];
+}
+
+// Ascending compaction: block b writes its active indices at offsets[b] + rank, where the
+// rank comes from the wavefront ballot (mbcnt) plus the preceding wavefronts' popcounts.
+__global__ __launch_bounds__(256) void thin_scatter_kernel(ThinListArgs a) {
+    __shared__ int wsum[4];
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool act = (p < a.N) && ((int)a.cnt[p] < a.hyst);
+    unsigned long long m = __ballot(act);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int base = a.block_offsets[blockIdx.x];
+    for (int w = 0; w < wv; ++w) base += wsum[w];
+    unsigned long long below = lane ? (m & ((~0ull) >> (64 - lane))) : 0ull;
+    if (act) a.plist[base + __popcll(below)] = (int32_t)p;
+}
+
+// Tile list: ascending ids of flagged tiles (one workgroup), and clear the flags.
+__global__ __launch_bounds__(1024) void tile_compact_kernel(int32_t* tflag, int n,
+                                                            int32_t* tlist, int64_t* count) {
+    __shared__ int wsum[16];
+    __shared__ int base_s;
+    if (threadIdx.x == 0) base_s = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int t0 = 0; t0 < n; t0 += 1024) {
+        int t = t0 + threadIdx.x;
+        bool on = t < n && tflag[t] != 0;
+        unsigned long long m = __ballot(on);
+        if (lane == 0) wsum[wv] = __popcll(m);
+        __syncthreads();
+        int base = base_s;
+        for (int w = 0; w < wv; ++w) base += wsum[w];
+        unsigned long long below = lane ? (m & ((~0ull) >> (64 - lane))) : 0ull;
+        if (on) {
+            tlist[base + __popcll(below)] = t;
+            tflag[t] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            base_s += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base_s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Deterministic FP64 reductions (flux, active count) and small utilities.
+// ---------------------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// partial[b] = sum of u over the elements b*256 + t + j*RED_BLOCKS*256 (fixed order)
+__global__ __launch_bounds__(256) void reduce_sum_kernel(const float* u, int64_t N,
+                                                         double* partial) {
+    __shared__ double ws[4];
+    double s = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N;
+         p += (int64_t)RED_BLOCKS * 256)
+        s += (double)u[p];
+    s = wave_sum_f64(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+__global__ __launch_bounds__(256) void count_active_kernel(const uint8_t* cnt, int64_t N,
+                                                           int hyst, int64_t* partial_i) {
+    __shared__ int64_t ws[4];
+    int64_t s = 0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N;
+         p += (int64_t)RED_BLOCKS * 256)
+        s += ((int)cnt[p] < hyst) ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial_i[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void final_reduce_kernel(const double* partial,
+                                                           const int64_t* partial_i,
+                                                           double* out_d, int64_t* out_i) {
+    __shared__ double ds[256];
+    __shared__ int64_t is[256];
+    double s = 0.0;
+    int64_t c = 0;
+    for (int b = threadIdx.x; b < RED_BLOCKS; b += 256) {
+        s += partial[b];
+        if (partial_i) c += partial_i[b];
+    }
+    ds[threadIdx.x] = s;
+    is[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            ds[threadIdx.x] += ds[threadIdx.x + off];
+            is[threadIdx.x] += is[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out_d = ds[0];
+        if (out_i) *out_i = is[0];
+    }
+}
+
+// f must be finite and >= 0; sets *flag = 1 otherwise.
+__global__ __launch_bounds__(256) void check_f_kernel(const float* f, int64_t N, int32_t* flag) {
+    int bad = 0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * 256) {
+        float v = f[p];
+        if (!(v >= 0.f) || isinf(v)) bad = 1;
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(256) void copy_f32_kernel(float* dst, const float* src, int64_t n) {
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * 256)
+        dst[p] = src[p];
+}
+
+__global__ __launch_bounds__(256) void copy_u8_kernel(uint8_t* dst, const uint8_t* src, int64_t n) {
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * 256)
+        dst[p] = src[p];
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* dst, uint32_t v, int64_t n) {
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * 256)
+        dst[p] = v;
+}
+
+__global__ void set_i64_kernel(int64_t* dst, int64_t v) { *dst = v; }
+
+}  // namespace rlk

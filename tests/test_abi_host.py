@@ -1,0 +1,144 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads and exports every
+symbol include/rl.h declares; the PSF compiler's run list equals the oracle-side
+definition bit for bit (P13); parameter validation returns the documented status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1304_7211_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1304_7211_amd import build
+        build.build()
+    _abi.lib()
+    return _abi
+
+
+def test_exports_every_declared_symbol(A):
+    hdr = open(os.path.join(ROOT, "include", "rl.h")).read()
+    declared = set(re.findall(r"\b(rl_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations parsed"
+    L = ctypes.CDLL(A.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} declared in rl.h but not exported"
+    assert declared == set(A.EXPORTS)
+
+
+def test_status_strings(A):
+    assert A.status_str(0) == "RL_OK"
+    assert A.status_str(-1) == "RL_E_INVAL"
+    assert A.status_str(-5) == "RL_E_UNSUPPORTED"
+    assert A.status_str(42) == "RL_E_UNKNOWN"
+
+
+def _psfs():
+    yield synth.delta()
+    for L in (2, 5, 15, 41, 63):
+        yield synth.box_h(L)
+        yield synth.box_v(L)
+    for r in (1, 3, 4, 8, 10, 16, 24):
+        yield synth.disc(r)
+    for L, a in ((9, 0.0), (31, 30.0), (47, 75.0), (17, 45.0), (13, 90.0), (25, 137.0)):
+        yield synth.oblique_line(L, a)
+    yield synth.dense_random(15, 3)
+    yield synth.box_rect(5, 7)
+    yield np.array([[0, 1, 1, 2, 0, 3], [0, 0, 0, 0, 0, 0], [5, 5, 5, 5, 5, 5]], np.float32)
+
+
+def test_p13_run_list_matches_oracle_definition(A):
+    for h in _psfs():
+        ints, ws = oracle.psf_runs(h)
+        runs, w, cls = A.rl_psf_runs(np.ascontiguousarray(h))
+        assert np.array_equal(runs, ints), h.shape
+        assert np.array_equal(w.view(np.uint32), ws.view(np.uint32))
+
+
+def test_auto_classification(A):
+    assert A.rl_psf_runs(synth.delta())[2] == A.RL_PATH_DIRECT
+    assert A.rl_psf_runs(synth.box_h(15))[2] == A.RL_PATH_BOX_AXIS
+    assert A.rl_psf_runs(synth.box_v(41))[2] == A.RL_PATH_BOX_AXIS
+    assert A.rl_psf_runs(synth.disc(10))[2] == A.RL_PATH_RUNS
+    assert A.rl_psf_runs(synth.oblique_line(31, 30.0))[2] == A.RL_PATH_RUNS
+    assert A.rl_psf_runs(synth.dense_random(15, 1))[2] == A.RL_PATH_RUNS
+    # a vertical line with gaps is not a box
+    h = np.zeros((5, 1), np.float32)
+    h[[0, 1, 3, 4]] = 0.25
+    assert A.rl_psf_runs(h)[2] == A.RL_PATH_RUNS
+
+
+def _params(A, H=64, W=48, psf=None, **kw):
+    psf = synth.disc(3) if psf is None else np.ascontiguousarray(psf, np.float32)
+    p = A.rl_params()
+    p.height, p.width = H, W
+    p.f = 0
+    p.psf_h, p.psf_w = psf.shape
+    p.psf = psf.ctypes.data
+    p.boundary = kw.get("boundary", 0)
+    p.path = kw.get("path", 0)
+    p.schedule = kw.get("schedule", 0)
+    p.kahan = 1
+    if "thin" in kw:
+        p.thin.mode, p.thin.tau, p.thin.hysteresis, p.thin.reset_period, \
+            p.thin.compact_period = kw["thin"]
+    return p, psf
+
+
+def _ws_status(A, p):
+    n = ctypes.c_size_t(0)
+    return A.lib().rl_workspace_bytes(ctypes.byref(p), ctypes.byref(n)), n.value
+
+
+def test_workspace_bytes_and_validation(A):
+    p, keep = _params(A)
+    st, n = _ws_status(A, p)
+    assert st == A.RL_OK and n >= 3 * 64 * 48 * 4
+    # thinning adds counters, lists and the schedule ring
+    p2, keep2 = _params(A, thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
+    st2, n2 = _ws_status(A, p2)
+    assert st2 == A.RL_OK and n2 > n
+    bad = []
+    p, k1 = _params(A, H=0)
+    bad.append(p)
+    p, k2 = _params(A, psf=np.array([[0.5, -0.1, 0.6]], np.float32))
+    bad.append(p)
+    p, k3 = _params(A, psf=np.array([[0.5, np.nan]], np.float32))
+    bad.append(p)
+    p, k4 = _params(A, psf=np.zeros((3, 3), np.float32))
+    bad.append(p)
+    p, k5 = _params(A, psf=synth.disc(3), path=A.RL_PATH_BOX_AXIS)
+    bad.append(p)
+    p, k6 = _params(A, boundary=7)
+    bad.append(p)
+    p, k7 = _params(A, thin=(A.RL_THIN_REL, 1e-4, 0, 10, 10))
+    bad.append(p)
+    for q in bad:
+        assert _ws_status(A, q)[0] == A.RL_E_INVAL
+    p, k8 = _params(A, psf=synth.box_h(9), schedule=A.RL_SCHED_RESIDENT,
+                    thin=(A.RL_THIN_ABS, 0.1, 1, 10, 1))
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k9 = _params(A, psf=synth.box_h(9), schedule=A.RL_SCHED_RESIDENT)
+    assert _ws_status(A, p)[0] == A.RL_OK
+
+
+def test_null_and_state_errors(A):
+    L = A.lib()
+    assert L.rl_iterate(None, 1) == A.RL_E_INVAL
+    assert L.rl_destroy(None) == A.RL_E_INVAL
+    assert L.rl_result(None, None, None) == A.RL_E_INVAL
+    p, keep = _params(A)
+    job = ctypes.c_void_p(0)
+    # NULL workspace / NULL f are rejected before any device work
+    assert L.rl_init(ctypes.byref(p), None, 0, ctypes.byref(job)) == A.RL_E_INVAL
+    n = ctypes.c_int32(0)
+    assert L.rl_psf_runs(np.zeros((2, 2), np.float32).ctypes.data, 2, 2, None, None, 0,
+                         ctypes.byref(n), None) == A.RL_E_INVAL
