@@ -549,11 +549,6 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
                 rl_status st = rebuild_lists(j);
                 if (st) return st;
             }
-            // zero the ring slot of the next iteration (phase B of this one adds to slot k)
-            int64_t* slot = j->at<int64_t>(j->L.sched) + ((j->k + 1) % rlk::SCHED_RING);
-            rl_status st = dev_err(launch("ring_zero", rlk::set_i64_kernel, dim3(1), dim3(1), 0, s,
-                                          slot, (int64_t)0), "ring_zero");
-            if (st) return st;
         }
         PhaseArgs aa = phase_args(j, false, thin, full);
         PhaseArgs ab = phase_args(j, true, thin, full);

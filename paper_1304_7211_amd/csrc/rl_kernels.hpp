@@ -118,8 +118,13 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 }
 
 // Resolve this workgroup's tile (a0, b0); returns false if it has none.
+// Thinned mode: the first thread of phase A also clears the active-count ring slot of
+// iteration k + 1 (phase B of iteration k adds into slot k).
+template <bool PHASE_B>
 __device__ __forceinline__ bool resolve_tile(const PhaseArgs& p, int TA, int TB, int& a0,
                                              int& b0) {
+    if (!PHASE_B && p.sched && blockIdx.x == 0 && threadIdx.x == 0)
+        p.sched[(p.k + 1) % SCHED_RING] = 0;
     int n;
     if (p.tile_list) n = (int)*p.tile_count;
     else n = p.tiles_a * p.tiles_b;
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(PhaseArgs p) {
     extern __shared__ float lds[];
     constexpr int TA = 64, TB = NW * S;
     int a0, b0;
-    if (!resolve_tile(p, TA, TB, a0, b0)) return;
+    if (!resolve_tile<PHASE_B>(p, TA, TB, a0, b0)) return;
     TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, LMAX - 1);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(PhaseArgs p) {
     extern __shared__ float lds[];
     constexpr int TA = 64, TB = NW * S;
     int a0, b0;
-    if (!resolve_tile(p, TA, TB, a0, b0)) return;
+    if (!resolve_tile<PHASE_B>(p, TA, TB, a0, b0)) return;
     TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
