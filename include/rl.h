@@ -159,14 +159,21 @@ rl_status rl_result(rl_job *job, float *u_out, rl_stats *st);
 rl_status rl_destroy(rl_job *job);
 
 /*
- * Batched iteration: enqueue n_iter[j] iterations of every job j in ONE stream, with
- * each iteration's kernels covering all jobs that still have iterations left in one
- * launch per phase.  Jobs must have been created with thinning off and the two-pass
- * schedule (any path).  The per-launch work tables live in the batch workspace:
- *   rl_batch_workspace_bytes(jobs, n_jobs, &bytes), then rl_iterate_batch(..., bws, bytes).
+ * Batched iteration of uneven jobs (different sizes, PSFs, iteration counts, thinning).
+ * Enqueues n_iter[j] >= 0 further iterations of every job j on `stream` (hipStream_t;
+ * the caller orders it against the jobs' own streams).  Jobs on the tiled two-pass
+ * schedule are grouped by kernel variant; each batch iteration then runs ONE launch per
+ * phase and group, covering the tiles of every job of the group that still has
+ * iterations left (jobs are ordered by remaining iterations, so finished jobs drop out
+ * of the grid).  Jobs on the resident schedule run all their iterations in one launch
+ * each.  The per-group work tables (job descriptors and tile prefix sums) are copied into
+ * the caller's batch workspace `bws` (device, 256-byte aligned) of at least
+ * rl_batch_workspace_bytes(n_jobs) bytes; `bws` must not be reused by another call
+ * before this one's work has started on the stream (the library waits for its own
+ * previous upload into the same `bws`).  A job may appear at most once (RL_E_INVAL).
  * Results per job are bit-identical to rl_iterate on that job alone.
  */
-rl_status rl_batch_workspace_bytes(rl_job *const *jobs, int32_t n_jobs, size_t *bytes);
+rl_status rl_batch_workspace_bytes(int32_t n_jobs, size_t *bytes);
 rl_status rl_iterate_batch(rl_job *const *jobs, const int32_t *n_iter, int32_t n_jobs,
                            void *bws, size_t bws_bytes, void *stream);
 

@@ -89,7 +89,7 @@ def lib():
             "rl_iterate": (i32, [vp, i32]),
             "rl_result": (i32, [vp, vp, P(rl_stats)]),
             "rl_destroy": (i32, [vp]),
-            "rl_batch_workspace_bytes": (i32, [P(vp), i32, P(sz)]),
+            "rl_batch_workspace_bytes": (i32, [i32, P(sz)]),
             "rl_iterate_batch": (i32, [P(vp), P(i32), i32, vp, sz, vp]),
             "rl_get_state": (i32, [vp, vp, vp, vp, P(i64)]),
             "rl_set_state": (i32, [vp, vp, vp, vp, i64]),
@@ -150,10 +150,9 @@ def rl_destroy(job):
     return check("rl_destroy", lib().rl_destroy(ctypes.c_void_p(job)))
 
 
-def rl_batch_workspace_bytes(jobs):
-    arr = (ctypes.c_void_p * len(jobs))(*jobs)
+def rl_batch_workspace_bytes(n_jobs):
     n = ctypes.c_size_t(0)
-    check("rl_batch_workspace_bytes", lib().rl_batch_workspace_bytes(arr, len(jobs),
+    check("rl_batch_workspace_bytes", lib().rl_batch_workspace_bytes(int(n_jobs),
                                                                       ctypes.byref(n)))
     return n.value
 

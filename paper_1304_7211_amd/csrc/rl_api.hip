@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -53,7 +55,7 @@ struct Config {
 
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
-        bcounts, boffs, ctr, sched, red, red_i, total;
+        bcounts, boffs, ctr, sched, red, red_i, args, prefix, total;
 };
 
 // counters block (int64 slots)
@@ -286,6 +288,8 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
         L.sched = take(rlk::SCHED_RING * 8);
     }
     L.ctr = take(C_COUNT * 8);
+    L.args = take(2 * sizeof(PhaseArgs));
+    L.prefix = take(2 * sizeof(int32_t));
     L.red = take(rlk::RED_BLOCKS * 8);
     L.red_i = take(rlk::RED_BLOCKS * 8);
     L.total = o;
@@ -322,6 +326,8 @@ struct rl_job {
     bool live;
     std::vector<DevSpan> h_conv, h_corr;
     std::vector<float> h_conv_w, h_corr_w;
+    PhaseArgs h_args[2];
+    int32_t h_prefix[2];
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -371,7 +377,7 @@ unsigned grid_for(int64_t n, int64_t per = 256, int64_t cap = 4096) {
 }
 
 // ---- kernel instantiation tables --------------------------------------------------------
-using PhaseFn = void (*)(PhaseArgs);
+using PhaseFn = void (*)(rlk::LaunchArgs);
 
 template <int O, int S, bool B>
 PhaseFn span_fn(int lmax) {
@@ -436,7 +442,8 @@ ResFn resident_fn(int orient, int seg) {
     return nullptr;
 }
 
-PhaseArgs phase_args(rl_job* j, bool phase_b, bool thin, bool full) {
+// Device table entry of one phase of a job (base iteration index k0).
+PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     PhaseArgs a{};
     const Config& c = j->cfg;
     const rl::OpTable& t = phase_b ? c.corr : c.conv;
@@ -457,24 +464,23 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, bool thin, bool full) {
     a.c_max = t.c_max;
     a.tiles_a = c.tiles_a;
     a.tiles_b = c.tiles_b;
-    a.k = j->k;
-    if (thin) {
+    a.k = k0;
+    a.full = 1;
+    if (j->p.thin.mode != RL_THIN_OFF) {
         a.cnt = j->at<uint8_t>(j->L.cnt);
         a.thin_mode = j->p.thin.mode;
         a.hyst = j->p.thin.hysteresis;
+        a.reset_period = j->p.thin.reset_period;
         a.tau = j->p.thin.tau;
-        a.full = full ? 1 : 0;
         a.sched = j->at<int64_t>(j->L.sched);
         a.active_total = j->at<int64_t>(j->L.ctr) + C_ACTIVE_TOTAL;
-        if (!full) {
-            a.tile_list = j->at<int32_t>(j->L.tlist);
-            a.tile_count = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
-        }
+        a.tile_list = j->at<int32_t>(j->L.tlist);
+        a.tile_count = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
     }
     return a;
 }
 
-rl_status rebuild_lists(rl_job* j) {
+rl_status rebuild_lists(rl_job* j, hipStream_t s) {
     rlk::ThinListArgs a{};
     a.cnt = j->at<uint8_t>(j->L.cnt);
     a.N = j->N;
@@ -491,7 +497,6 @@ rl_status rebuild_lists(rl_job* j) {
     a.plist_len = j->at<int64_t>(j->L.ctr) + C_PLIST_LEN;
     const int nb = (int)thin_blocks(j->N);
     a.n_blocks = nb;
-    hipStream_t s = j->stream;
     rl_status st;
     if ((st = dev_err(launch("thin_count", rlk::thin_count_kernel, dim3(nb), dim3(256), 0, s, a), "thin_count"))) return st;
     if ((st = dev_err(launch("thin_scan", rlk::scan_counts_kernel, dim3(1), dim3(1024), 0, s,
@@ -540,25 +545,40 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
     PhaseFn fa = phase_fn(c, false), fb = phase_fn(c, true);
     const char* na = phase_name(c, false);
     const char* nbn = phase_name(c, true);
+    rlk::LaunchArgs la{}, lb{};
+    la.table = j->at<PhaseArgs>(j->L.args);
+    lb.table = la.table + 1;
+    la.prefix = lb.prefix = j->at<int32_t>(j->L.prefix);
+    la.n_jobs = lb.n_jobs = 1;
     for (int i = 0; i < n; ++i) {
-        bool full = true;
-        if (thin) {
-            full = is_full(j->k, j->p.thin.reset_period);
-            if (!full && (!j->list_valid ||
-                          is_rebuild(j->k, j->p.thin.reset_period, j->p.thin.compact_period))) {
-                rl_status st = rebuild_lists(j);
-                if (st) return st;
-            }
+        if (thin && !is_full(j->k, j->p.thin.reset_period) &&
+            (!j->list_valid ||
+             is_rebuild(j->k, j->p.thin.reset_period, j->p.thin.compact_period))) {
+            rl_status st = rebuild_lists(j, s);
+            if (st) return st;
         }
-        PhaseArgs aa = phase_args(j, false, thin, full);
-        PhaseArgs ab = phase_args(j, true, thin, full);
-        rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, aa), na);
+        la.kb = lb.kb = j->k;
+        rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, la), na);
         if (st) return st;
-        st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, ab), nbn);
+        st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lb), nbn);
         if (st) return st;
         j->k += 1;
     }
     return RL_OK;
+}
+
+struct BatchStage {
+    std::vector<char> host;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+std::mutex g_bmu;
+std::map<void*, BatchStage> g_stage;
+
+// Upper bound of the batch tables: per group two PhaseArgs arrays and a prefix array,
+// each 256-byte aligned; at most one group per job.
+size_t batch_bytes(int32_t n_jobs) {
+    return (size_t)n_jobs * (2 * sizeof(PhaseArgs) + 3 * kAlign + 2 * sizeof(int32_t)) + kAlign;
 }
 
 std::vector<DevSpan> to_dev(const rl::OpTable& t) {
@@ -639,6 +659,15 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.conv_w), j->h_conv_w.data(), j->h_conv_w.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_w), j->h_corr_w.data(), j->h_corr_w.size() * 4, hipMemcpyHostToDevice, s);
     if ((st = dev_err(e, "upload PSF"))) { delete j; return st; }
+    if (j->cfg.kind != KIND_RESIDENT) {
+        j->h_args[0] = phase_args(j, false, 0);
+        j->h_args[1] = phase_args(j, true, 0);
+        j->h_prefix[0] = 0;
+        j->h_prefix[1] = j->cfg.tiles_a * j->cfg.tiles_b;
+        e = hipMemcpyAsync(j->at<void>(j->L.args), j->h_args, sizeof j->h_args, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.prefix), j->h_prefix, sizeof j->h_prefix, hipMemcpyHostToDevice, s);
+        if ((st = dev_err(e, "upload args"))) { delete j; return st; }
+    }
     const int64_t N = j->N;
     unsigned g = grid_for(N);
     if ((st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.f), p->f, N), "copy f"))) { delete j; return st; }
@@ -716,18 +745,142 @@ rl_status rl_destroy(rl_job* j) {
     return RL_OK;
 }
 
-rl_status rl_batch_workspace_bytes(rl_job* const* jobs, int32_t n_jobs, size_t* bytes) {
-    (void)jobs;
-    (void)n_jobs;
-    if (!bytes) return RL_E_INVAL;
-    *bytes = 0;
-    return RL_E_UNSUPPORTED;
+rl_status rl_batch_workspace_bytes(int32_t n_jobs, size_t* bytes) {
+    if (!bytes || n_jobs < 1) return RL_E_INVAL;
+    *bytes = batch_bytes(n_jobs);
+    return RL_OK;
 }
 
 rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n_jobs, void* bws,
                            size_t bws_bytes, void* stream) {
-    (void)jobs; (void)n_iter; (void)n_jobs; (void)bws; (void)bws_bytes; (void)stream;
-    return RL_E_UNSUPPORTED;
+    if (!jobs || !n_iter || n_jobs < 1 || !bws) return RL_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(bws) % kAlign) return RL_E_INVAL;
+    if (bws_bytes < batch_bytes(n_jobs)) return RL_E_NOMEM;
+    {
+        std::vector<rl_job*> seen(jobs, jobs + n_jobs);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return RL_E_INVAL;
+    }
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        if (!jobs[i] || !jobs[i]->live) return RL_E_STATE;
+        if (n_iter[i] < 0) return RL_E_INVAL;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    rl_status st;
+    // jobs on the resident schedule run their iterations in one launch each
+    std::vector<int> tiled;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        rl_job* j = jobs[i];
+        if (j->cfg.kind == KIND_RESIDENT) {
+            hipStream_t keep = j->stream;
+            j->stream = s;
+            st = enqueue_iterations(j, n_iter[i]);
+            j->stream = keep;
+            if (st) return st;
+        } else {
+            tiled.push_back(i);
+        }
+    }
+    if (tiled.empty()) return RL_OK;
+    // group by kernel variant; inside a group, jobs with more iterations left come first,
+    // so the jobs still running at batch iteration kb are always a prefix of the group
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    for (int i : tiled) {
+        const Config& c = jobs[i]->cfg;
+        groups[std::make_tuple(c.kind, c.orient, c.S, c.lmax)].push_back(i);
+    }
+    struct G {
+        std::vector<int> idx;
+        std::vector<int32_t> prefix;
+        size_t off_a, off_b, off_p;
+        size_t lds_a = 0, lds_b = 0;
+        PhaseFn fa, fb;
+        const char *na, *nb;
+    };
+    std::vector<G> gs;
+    size_t off = 0;
+    for (auto& kv : groups) {
+        G g;
+        g.idx = kv.second;
+        std::stable_sort(g.idx.begin(), g.idx.end(),
+                         [&](int a, int b) { return n_iter[a] > n_iter[b]; });
+        g.prefix.push_back(0);
+        for (int i : g.idx) {
+            const Config& c = jobs[i]->cfg;
+            g.prefix.push_back(g.prefix.back() + c.tiles_a * c.tiles_b);
+            g.lds_a = std::max(g.lds_a, c.lds_a);
+            g.lds_b = std::max(g.lds_b, c.lds_b);
+        }
+        const Config& c0 = jobs[g.idx[0]]->cfg;
+        g.fa = phase_fn(c0, false);
+        g.fb = phase_fn(c0, true);
+        g.na = phase_name(c0, false);
+        g.nb = phase_name(c0, true);
+        g.off_a = off;
+        off = align_up(off + g.idx.size() * sizeof(PhaseArgs));
+        g.off_b = off;
+        off = align_up(off + g.idx.size() * sizeof(PhaseArgs));
+        g.off_p = off;
+        off = align_up(off + g.prefix.size() * sizeof(int32_t));
+        gs.push_back(std::move(g));
+    }
+    // stage the tables on the host and copy them in; the staging buffer of this batch
+    // workspace is reused only after its previous copy has completed
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        BatchStage& bs = g_stage[bws];
+        if (bs.pending) {
+            if ((st = dev_err(hipEventSynchronize(bs.done), "batch staging"))) return st;
+            bs.pending = false;
+        }
+        if (!bs.done && (st = dev_err(hipEventCreateWithFlags(&bs.done, hipEventDisableTiming), "event"))) return st;
+        bs.host.assign(off, 0);
+        for (const G& g : gs) {
+            PhaseArgs* ta = reinterpret_cast<PhaseArgs*>(bs.host.data() + g.off_a);
+            PhaseArgs* tb = reinterpret_cast<PhaseArgs*>(bs.host.data() + g.off_b);
+            for (size_t q = 0; q < g.idx.size(); ++q) {
+                rl_job* j = jobs[g.idx[q]];
+                ta[q] = phase_args(j, false, j->k);
+                tb[q] = phase_args(j, true, j->k);
+            }
+            std::memcpy(bs.host.data() + g.off_p, g.prefix.data(), g.prefix.size() * sizeof(int32_t));
+        }
+        hipError_t e = hipMemcpyAsync(bws, bs.host.data(), off, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(bs.done, s);
+        if ((st = dev_err(e, "batch tables"))) return st;
+        bs.pending = true;
+    }
+    int32_t kmax = 0;
+    for (int i : tiled) kmax = std::max(kmax, n_iter[i]);
+    char* base = static_cast<char*>(bws);
+    for (int32_t kb = 0; kb < kmax; ++kb) {
+        for (const G& g : gs)
+            for (int i : g.idx) {
+                rl_job* j = jobs[i];
+                if (n_iter[i] <= kb || j->p.thin.mode == RL_THIN_OFF) continue;
+                const int64_t k = j->k + kb;
+                if (!is_full(k, j->p.thin.reset_period) &&
+                    (!j->list_valid || is_rebuild(k, j->p.thin.reset_period, j->p.thin.compact_period)))
+                    if ((st = rebuild_lists(j, s))) return st;
+            }
+        for (int phase = 0; phase < 2; ++phase)
+            for (const G& g : gs) {
+                int m = 0;
+                while (m < (int)g.idx.size() && n_iter[g.idx[m]] > kb) ++m;
+                if (!m) continue;
+                rlk::LaunchArgs la{};
+                la.table = reinterpret_cast<const PhaseArgs*>(base + (phase ? g.off_b : g.off_a));
+                la.prefix = reinterpret_cast<const int32_t*>(base + g.off_p);
+                la.n_jobs = m;
+                la.kb = kb;
+                st = dev_err(launch(phase ? g.nb : g.na, phase ? g.fb : g.fa, dim3(g.prefix[m]),
+                                    dim3(kNW * 64), phase ? g.lds_b : g.lds_a, s, la),
+                             phase ? g.nb : g.na);
+                if (st) return st;
+            }
+    }
+    for (int i : tiled) jobs[i]->k += n_iter[i];
+    return RL_OK;
 }
 
 rl_status rl_get_state(rl_job* j, float* u, float* r, uint8_t* cnt, int64_t* k_out) {

@@ -86,6 +86,8 @@ __device__ __forceinline__ float rl_ratio(float f, float v) {
     return v > 0.f ? __fdiv_rn(f, v) : 0.f;
 }
 
+// Everything a phase kernel needs to know about one job.  Lives in device memory (the
+// job's workspace, or a batch table) and is read with scalar loads.
 struct PhaseArgs {
     int32_t H, W, bc, kahan;
     const float* src;     // u^k (phase A) or r (phase B)
@@ -98,14 +100,41 @@ struct PhaseArgs {
     int32_t n_spans;
     int32_t lane_min, lane_max, c_min, c_max;
     int32_t tiles_a, tiles_b;      // tile grid (lane axis, strip axis)
-    const int32_t* tile_list;      // thinned non-full step: list of tile ids, else NULL
+    const int32_t* tile_list;      // thinned: list of tile ids (used on non-full steps)
     const int64_t* tile_count;     // its length (device)
-    int32_t thin_mode, hyst, full; // thinning
+    int32_t thin_mode, hyst, reset_period, full;  // thinning (full is derived per launch)
     float tau;
+    int32_t pad0;
     int64_t* sched;                // active-count ring (thinning)
     int64_t* active_total;         // running sum of |A_k|
-    int64_t k;                     // iteration index
+    int64_t k;                     // base iteration index (plus LaunchArgs::kb)
 };
+
+// One launch covers the tiles of n_jobs jobs: job j owns workgroups
+// [prefix[j], prefix[j+1]).  kb is added to every job's base iteration index.
+struct LaunchArgs {
+    const PhaseArgs* table;
+    const int32_t* prefix;
+    int32_t n_jobs, pad;
+    int64_t kb;
+};
+
+typedef const __attribute__((address_space(4))) PhaseArgs* ConstArgsPtr;
+typedef const __attribute__((address_space(4))) int32_t* ConstIntPtr;
+
+__device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
+    PhaseArgs p;
+    p.H = t->H; p.W = t->W; p.bc = t->bc; p.kahan = t->kahan;
+    p.src = t->src; p.f = t->f; p.r = t->r; p.u = t->u; p.cnt = t->cnt;
+    p.spans = t->spans; p.wts = t->wts; p.n_spans = t->n_spans;
+    p.lane_min = t->lane_min; p.lane_max = t->lane_max; p.c_min = t->c_min; p.c_max = t->c_max;
+    p.tiles_a = t->tiles_a; p.tiles_b = t->tiles_b;
+    p.tile_list = t->tile_list; p.tile_count = t->tile_count;
+    p.thin_mode = t->thin_mode; p.hyst = t->hyst; p.reset_period = t->reset_period;
+    p.full = t->full; p.tau = t->tau; p.pad0 = 0;
+    p.sched = t->sched; p.active_total = t->active_total; p.k = t->k;
+    return p;
+}
 
 // Map a workgroup index to a tile so that each XCD (workgroups are dispatched to the 8
 // XCDs round-robin) gets one contiguous range of tiles: neighbouring tiles share halo
@@ -117,23 +146,38 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return start + idx;
 }
 
-// Resolve this workgroup's tile (a0, b0); returns false if it has none.
-// Thinned mode: the first thread of phase A also clears the active-count ring slot of
-// iteration k + 1 (phase B of iteration k adds into slot k).
+// Find this workgroup's job and tile.  Returns false if the workgroup has no tile (thinned
+// steps launch one workgroup per tile of the grid and use only as many as the list has).
+// Thinned mode: iteration k is full when k == 0 or k % R == 0; on other steps the tiles
+// come from the compacted list.  The first workgroup of a job in phase A also clears the
+// active-count ring slot of iteration k + 1 (phase B of iteration k adds into slot k).
 template <bool PHASE_B>
-__device__ __forceinline__ bool resolve_tile(const PhaseArgs& p, int TA, int TB, int& a0,
-                                             int& b0) {
-    if (!PHASE_B && p.sched && blockIdx.x == 0 && threadIdx.x == 0)
-        p.sched[(p.k + 1) % SCHED_RING] = 0;
-    int n;
-    if (p.tile_list) n = (int)*p.tile_count;
-    else n = p.tiles_a * p.tiles_b;
-    int nb = gridDim.x;
-    if ((int)blockIdx.x >= nb) return false;
-    // the remap is only a permutation when every block has a tile; otherwise go linear
-    int slot = (n == nb) ? xcd_tile(blockIdx.x, nb) : (int)blockIdx.x;
+__device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int TA, int TB,
+                                        int& a0, int& b0) {
+    const ConstIntPtr pre = (ConstIntPtr)L.prefix;
+    int lo = 0, hi = L.n_jobs - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {  // last job with prefix <= b
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    p = load_args((ConstArgsPtr)L.table + lo);
+    const int local = b - pre[lo];
+    const int nb_job = pre[lo + 1] - pre[lo];
+    p.k += L.kb;
+    bool use_list = false;
+    if (p.cnt) {
+        p.full = (p.k == 0 || (p.reset_period > 0 && p.k % p.reset_period == 0)) ? 1 : 0;
+        use_list = !p.full;
+        if (!PHASE_B && local == 0 && threadIdx.x == 0) p.sched[(p.k + 1) % SCHED_RING] = 0;
+    } else {
+        p.full = 1;
+    }
+    const int n = use_list ? (int)*p.tile_count : p.tiles_a * p.tiles_b;
+    const int slot = (L.n_jobs == 1 && !use_list && n == nb_job) ? xcd_tile(local, nb_job) : local;
     if (slot >= n) return false;
-    int t = p.tile_list ? p.tile_list[slot] : slot;
+    const int t = use_list ? p.tile_list[slot] : slot;
     a0 = (t % p.tiles_a) * TA;
     b0 = (t / p.tiles_a) * TB;
     return true;
@@ -338,11 +382,12 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
 // (kahan = 1) or plainly.  LMAX = 1 with the per-tap table is the DIRECT path.
 // ---------------------------------------------------------------------------------------
 template <int ORIENT, int S, int LMAX, int NW, bool PHASE_B>
-__global__ __launch_bounds__(NW * 64) void span_kernel(PhaseArgs p) {
+__global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     extern __shared__ float lds[];
     constexpr int TA = 64, TB = NW * S;
     int a0, b0;
-    if (!resolve_tile<PHASE_B>(p, TA, TB, a0, b0)) return;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, TA, TB, a0, b0)) return;
     TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, LMAX - 1);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
@@ -398,11 +443,12 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(PhaseArgs p) {
 // Kahan-compensated running sum (kahan = 1) or a plain one.
 // ---------------------------------------------------------------------------------------
 template <int ORIENT, int S, int NW, bool PHASE_B>
-__global__ __launch_bounds__(NW * 64) void slide_kernel(PhaseArgs p) {
+__global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
     extern __shared__ float lds[];
     constexpr int TA = 64, TB = NW * S;
     int a0, b0;
-    if (!resolve_tile<PHASE_B>(p, TA, TB, a0, b0)) return;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, TA, TB, a0, b0)) return;
     TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);

@@ -125,3 +125,26 @@ def deconvolve(f, psf, iters, **kw):
         return job.result()
     finally:
         job.close()
+
+
+class BatchRunner:
+    """Owns one batch workspace (torch uint8) sized for up to ``max_jobs`` jobs and runs
+    ``rl_iterate_batch`` on it."""
+
+    def __init__(self, max_jobs, device=None):
+        self.max_jobs = int(max_jobs)
+        self.nbytes = A.rl_batch_workspace_bytes(self.max_jobs)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8,
+                              device=device or torch.device("cuda:0"))
+
+    def iterate(self, jobs, n_iters, stream=None):
+        if len(jobs) > self.max_jobs:
+            raise ValueError("more jobs than the batch workspace was sized for")
+        handles = [j.handle for j in jobs]
+        A.rl_iterate_batch(handles, n_iters, self.ws.data_ptr(), self.ws.numel(),
+                           _stream_ptr(stream))
+
+
+def iterate_batch(jobs, n_iters, stream=None):
+    """One-shot batch: every job j advances by n_iters[j] iterations."""
+    BatchRunner(len(jobs), jobs[0].device).iterate(jobs, n_iters, stream)
