@@ -5,9 +5,11 @@ images from the seeded generator, Gaussian noise sigma 0.01, 200 RL iterations e
   (a) vertical motion blur, box of length 41      -> BOX_AXIS path
   (b) oblique motion line, length 31 at 30 deg, antialiased -> RUNS path (row spans)
   (c) uniform disc of radius 10                   -> RUNS path (sliding runs)
-A step runs all three jobs end to end through the C ABI: rl_init (copy f into the
-workspace, upload the compiled PSF), rl_iterate(200), rl_result (copy u^K out).  Inputs
-are resident on the GPU before the timed region starts.
+A step runs all three jobs end to end through the C ABI: rl_init for each (copy f into
+the workspace, upload the compiled PSF), one rl_iterate_batch call that advances all
+three by 200 iterations (independent kernel groups on concurrent streams), and rl_result
+for each (copy u^K out).  Inputs are resident on the GPU before the timed region starts.
+--mode sequential runs rl_iterate per job instead (the plain per-image method).
 
 Prints ONE JSON line.  Options: --gpus (must be 1), --steps, --warmup, --no-cpu-baseline,
 --no-kernel-timing.
@@ -56,6 +58,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--mode", choices=["batch", "sequential"], default="batch")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time the other mode (reported as 'other_mode')")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -67,7 +72,7 @@ def main():
 
     import synth
     from paper_1304_7211_amd import _abi as A
-    from paper_1304_7211_amd.job import Job
+    from paper_1304_7211_amd.job import BatchRunner, Job
 
     A.lib()  # fail loudly if the HIP library is not built
     dev = torch.device("cuda:0")
@@ -81,8 +86,9 @@ def main():
     px_it_step = sum(j["f"].size * j["iters"] for j in jobs)
 
     infos = {}
+    runner = BatchRunner(len(jobs))
 
-    def step():
+    def step_sequential():
         for j, f, o in zip(jobs, f_dev, outs):
             job = Job(f, j["psf"], path=j["path"])
             job.iterate(j["iters"])
@@ -90,33 +96,61 @@ def main():
             infos[j["name"]] = job.describe()
             job.close()
 
+    def step_batch():
+        js = [Job(f, j["psf"], path=j["path"]) for j, f in zip(jobs, f_dev)]
+        runner.iterate(js, [j["iters"] for j in jobs])
+        for j, jb, o in zip(jobs, js, outs):
+            jb.result(out=o)
+            infos[j["name"]] = jb.describe()
+            jb.close()
+
+    step = step_batch if args.mode == "batch" else step_sequential
+
     for w in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"bench: warmup {w + 1}/{args.warmup} done")
 
-    # timed region: kernel-level HIP events bracket every launch on its own stream
-    kt = not args.no_kernel_timing
-    if kt:
-        A.rl_timing_reset()
-        A.rl_timing_enable(True)
+    # timed region (no instrumentation)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if kt:
-        A.rl_timing_enable(False)
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = px_it_step * args.steps / elapsed
-    log(f"bench: {args.steps} steps in {elapsed:.4f}s -> {value:.4g} px-it/s")
+    log(f"bench: {args.steps} steps in {elapsed:.4f}s -> {value:.4g} px-it/s ({args.mode})")
+    other = None
+    if args.compare:
+        ostep = step_sequential if args.mode == "batch" else step_batch
+        ostep()
+        torch.cuda.synchronize()
+        o0 = time.perf_counter()
+        for _ in range(args.steps):
+            ostep()
+        torch.cuda.synchronize()
+        o1 = time.perf_counter()
+        other = dict(mode="sequential" if args.mode == "batch" else "batch",
+                     value=px_it_step * args.steps / (o1 - o0),
+                     ms_per_step=1e3 * (o1 - o0) / args.steps)
+        log(f"bench: other mode {other}")
 
-    # per-kernel durations (HIP events) and the dominant kernel's roofline
+    # per-kernel durations: the same steps again with every launch bracketed by HIP events
+    # on the stream it is launched on (events add a few microseconds per launch, so the
+    # headline value above comes from the uninstrumented run)
     roofline = None
     kernels = {}
+    kt = not args.no_kernel_timing
     if kt:
+        A.rl_timing_reset()
+        A.rl_timing_enable(True)
+        torch.cuda.synchronize()
+        for s in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        A.rl_timing_enable(False)
         names = ["resident_box", "slide_conv_ratio", "slide_corr_update", "span_conv_ratio",
                  "span_corr_update", "direct_conv_ratio", "direct_corr_update"]
         for nm in names:
@@ -173,6 +207,7 @@ def main():
         "data": "synthetic (seeded generator: shapes + sinusoid, reflect blur, Gaussian noise)",
         "config": {"workload": "specialised PSFs 1024x1024 x3 (vertical box 41, oblique 31@30deg AA, "
                                "disc r10), 200 iterations each",
+                   "mode": args.mode,
                    "px_it_per_step": px_it_step,
                    "paths": {k: {"path": A.PATH_NAMES[v["path"]],
                                  "schedule": A.SCHED_NAMES[v["schedule"]]}
@@ -180,6 +215,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "other_mode": other,
     }
     print(json.dumps(line), flush=True)
 
@@ -193,12 +229,14 @@ def cpu_baseline(jobs):
     t0 = time.perf_counter()
     sample = []
     for j in jobs:
-        k = 4
+        # about 5 s per job: iterations sized by a one-iteration probe
+        p0 = time.perf_counter()
+        o.rl(j["f"], j["psf"], 1)
+        one = max(time.perf_counter() - p0, 1e-3)
+        k = max(1, int(5.0 / one))
         o.rl(j["f"], j["psf"], k)
-        total_px_it += j["f"].size * k
-        sample.append(f"{j['name']} x{k} it")
-        if time.perf_counter() - t0 > 25.0:
-            break
+        total_px_it += j["f"].size * (k + 1)
+        sample.append(f"{j['name']} x{k + 1} it")
     dt = time.perf_counter() - t0
     log(f"bench: cpu oracle {total_px_it} px-it in {dt:.2f}s on {cores} threads")
     return dict(value=total_px_it / dt, unit="px-it/s", cores=cores, kind="oracle",

@@ -567,6 +567,26 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
     return RL_OK;
 }
 
+// Library-internal streams (non-blocking, default priority) on which independent groups
+// of a batch run concurrently; forked from and joined back to the caller's stream with
+// events.
+constexpr int kSideStreams = 8;
+std::mutex g_smu;
+hipStream_t g_side[kSideStreams] = {};
+hipEvent_t g_fork = nullptr;
+hipEvent_t g_join[kSideStreams] = {};
+
+rl_status side_streams(int n) {
+    std::lock_guard<std::mutex> lk(g_smu);
+    rl_status st;
+    if (!g_fork && (st = dev_err(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming), "event"))) return st;
+    for (int i = 0; i < n && i < kSideStreams; ++i) {
+        if (!g_side[i] && (st = dev_err(hipStreamCreateWithFlags(&g_side[i], hipStreamNonBlocking), "stream"))) return st;
+        if (!g_join[i] && (st = dev_err(hipEventCreateWithFlags(&g_join[i], hipEventDisableTiming), "event"))) return st;
+    }
+    return RL_OK;
+}
+
 struct BatchStage {
     std::vector<char> host;
     hipEvent_t done = nullptr;
@@ -767,21 +787,12 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     rl_status st;
-    // jobs on the resident schedule run their iterations in one launch each
-    std::vector<int> tiled;
+    std::vector<int> tiled, resident;
     for (int32_t i = 0; i < n_jobs; ++i) {
-        rl_job* j = jobs[i];
-        if (j->cfg.kind == KIND_RESIDENT) {
-            hipStream_t keep = j->stream;
-            j->stream = s;
-            st = enqueue_iterations(j, n_iter[i]);
-            j->stream = keep;
-            if (st) return st;
-        } else {
-            tiled.push_back(i);
-        }
+        if (jobs[i]->cfg.kind == KIND_RESIDENT) resident.push_back(i);
+        else tiled.push_back(i);
     }
-    if (tiled.empty()) return RL_OK;
+    if (tiled.empty() && resident.empty()) return RL_OK;
     // group by kernel variant; inside a group, jobs with more iterations left come first,
     // so the jobs still running at batch iteration kb are always a prefix of the group
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
@@ -845,39 +856,62 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
             }
             std::memcpy(bs.host.data() + g.off_p, g.prefix.data(), g.prefix.size() * sizeof(int32_t));
         }
-        hipError_t e = hipMemcpyAsync(bws, bs.host.data(), off, hipMemcpyHostToDevice, s);
+        hipError_t e = off ? hipMemcpyAsync(bws, bs.host.data(), off, hipMemcpyHostToDevice, s)
+                           : hipSuccess;
         if (e == hipSuccess) e = hipEventRecord(bs.done, s);
         if ((st = dev_err(e, "batch tables"))) return st;
         bs.pending = true;
     }
-    int32_t kmax = 0;
-    for (int i : tiled) kmax = std::max(kmax, n_iter[i]);
+    // fork: every group (and the resident jobs) gets its own stream after the table copy
+    const int n_streams = std::min<int>(kSideStreams, (int)gs.size() + (resident.empty() ? 0 : 1));
+    if ((st = side_streams(n_streams))) return st;
+    std::lock_guard<std::mutex> lk(g_smu);
+    if ((st = dev_err(hipEventRecord(g_fork, s), "fork"))) return st;
+    for (int q = 0; q < n_streams; ++q)
+        if ((st = dev_err(hipStreamWaitEvent(g_side[q], g_fork, 0), "fork wait"))) return st;
+    auto stream_of_group = [&](size_t gi) { return g_side[gi % n_streams]; };
+    // jobs on the resident schedule run all their iterations in one launch each
+    for (int i : resident) {
+        rl_job* j = jobs[i];
+        hipStream_t keep = j->stream;
+        j->stream = g_side[n_streams - 1];
+        st = enqueue_iterations(j, n_iter[i]);
+        j->stream = keep;
+        if (st) return st;
+    }
     char* base = static_cast<char*>(bws);
-    for (int32_t kb = 0; kb < kmax; ++kb) {
-        for (const G& g : gs)
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+        const G& g = gs[gi];
+        hipStream_t gsm = stream_of_group(gi);
+        const int32_t kmax = n_iter[g.idx[0]];
+        for (int32_t kb = 0; kb < kmax; ++kb) {
             for (int i : g.idx) {
                 rl_job* j = jobs[i];
                 if (n_iter[i] <= kb || j->p.thin.mode == RL_THIN_OFF) continue;
                 const int64_t k = j->k + kb;
                 if (!is_full(k, j->p.thin.reset_period) &&
                     (!j->list_valid || is_rebuild(k, j->p.thin.reset_period, j->p.thin.compact_period)))
-                    if ((st = rebuild_lists(j, s))) return st;
+                    if ((st = rebuild_lists(j, gsm))) return st;
             }
-        for (int phase = 0; phase < 2; ++phase)
-            for (const G& g : gs) {
-                int m = 0;
-                while (m < (int)g.idx.size() && n_iter[g.idx[m]] > kb) ++m;
-                if (!m) continue;
+            int m = 0;
+            while (m < (int)g.idx.size() && n_iter[g.idx[m]] > kb) ++m;
+            for (int phase = 0; phase < 2; ++phase) {
                 rlk::LaunchArgs la{};
                 la.table = reinterpret_cast<const PhaseArgs*>(base + (phase ? g.off_b : g.off_a));
                 la.prefix = reinterpret_cast<const int32_t*>(base + g.off_p);
                 la.n_jobs = m;
                 la.kb = kb;
                 st = dev_err(launch(phase ? g.nb : g.na, phase ? g.fb : g.fa, dim3(g.prefix[m]),
-                                    dim3(kNW * 64), phase ? g.lds_b : g.lds_a, s, la),
+                                    dim3(kNW * 64), phase ? g.lds_b : g.lds_a, gsm, la),
                              phase ? g.nb : g.na);
                 if (st) return st;
             }
+        }
+    }
+    // join
+    for (int q = 0; q < n_streams; ++q) {
+        if ((st = dev_err(hipEventRecord(g_join[q], g_side[q]), "join"))) return st;
+        if ((st = dev_err(hipStreamWaitEvent(s, g_join[q], 0), "join wait"))) return st;
     }
     for (int i : tiled) jobs[i]->k += n_iter[i];
     return RL_OK;
