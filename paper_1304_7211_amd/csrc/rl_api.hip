@@ -84,14 +84,14 @@ size_t tile_lds_bytes(const rl::OpTable& t, int orient, int TB, int extra) {
 
 // Cost estimate per output (VALU-op equivalents), used to pick kernel and orientation.
 double span_cost(const rl::OpTable& t, int S, int lmax, bool kahan) {
+    (void)lmax;
+    (void)kahan;
     double valu = 0, lds = 0;
-    int lines = 0;
     for (const rl::Span& s : t.spans) {
-        valu += lmax;
-        lds += double(S + lmax - 1) / S;
-        if (s.row_end) ++lines;
+        valu += s.len + 3.0;  // FMAs + per-piece address and descriptor work
+        lds += double(S + s.len - 1) / S;
+        if (s.row_end) valu += 1.0;
     }
-    valu += lines * (kahan ? 4.0 : 1.0);
     return std::max(valu, 2.0 * lds) + 8.0;
 }
 
@@ -182,9 +182,11 @@ rl_status choose_config(const rl_params* p, const rl::CompiledPsf& c, Config* cf
     const int64_t npx = (int64_t)H * W;
     // outputs per lane: long strips amortise seeds and windows, short strips give the
     // latency-bound kernels more wavefronts on small images
-    const int span_S = p->tuning.strip ? p->tuning.strip : (npx >= (int64_t)4 << 20 ? 16 : 8);
-    const int slide_S = p->tuning.strip ? p->tuning.strip : (npx >= (int64_t)4 << 20 ? 32 : 16);
-    if (span_S != 8 && span_S != 16 && span_S != 32) { *why = "tuning.strip"; return RL_E_INVAL; }
+    // defaults from measurements on 1024^2 and 2048^2 images (span: 8 outputs per lane;
+    // sliding runs: 8 below 4 Mpx, 16 from there on)
+    const int span_S = p->tuning.strip ? p->tuning.strip : 8;
+    const int slide_S = p->tuning.strip ? p->tuning.strip : (npx >= (int64_t)4 << 20 ? 16 : 8);
+    if (span_S != 4 && span_S != 8 && span_S != 16 && span_S != 32) { *why = "tuning.strip"; return RL_E_INVAL; }
     if (path == RL_PATH_DIRECT) {
         cfg->kind = KIND_SPAN;
         cfg->orient = rlk::ORIENT_ROWS;
@@ -215,7 +217,7 @@ rl_status choose_config(const rl_params* p, const rl::CompiledPsf& c, Config* cf
                     cfg->lmax = 0;
                 }
             }
-            for (int lm : {2, 4, 8, 16}) {
+            for (int lm : {4, 8, 16}) {
                 rl::OpTable t = rl::build_op_table(h, kh, kw, false, o, false, lm);
                 double cost = span_cost(t, std::min(span_S, 16), lm, kahan);
                 if (cost < best) {
@@ -235,14 +237,25 @@ rl_status choose_config(const rl_params* p, const rl::CompiledPsf& c, Config* cf
     }
     cfg->TA = 64;
     cfg->TB = kNW * cfg->S;
-    int extra = cfg->kind == KIND_SPAN ? cfg->lmax - 1 : 0;
-    cfg->lds_a = tile_lds_bytes(cfg->conv, cfg->orient, cfg->TB, extra);
-    cfg->lds_b = tile_lds_bytes(cfg->corr, cfg->orient, cfg->TB, extra);
+    const int extra = 0;  // windows never read past the last tap of a piece
+    auto lds_for = [&](const rl::OpTable& t) {
+        size_t b = tile_lds_bytes(t, cfg->orient, cfg->TB, extra);
+        if (cfg->kind == KIND_SLIDE) {
+            // tile plus the seed / strip-total exchange area (after the tile, not the stage)
+            size_t na = 64 + t.lane_max - t.lane_min, nb = cfg->TB + t.c_max - t.c_min + extra;
+            size_t ny = cfg->orient == rlk::ORIENT_ROWS ? na : nb;
+            size_t nx = cfg->orient == rlk::ORIENT_ROWS ? nb : na;
+            b = std::max(b, (ny * (nx | 1) + rlk::slide_scratch_floats<kNW>()) * sizeof(float));
+        }
+        return b;
+    };
+    cfg->lds_a = lds_for(cfg->conv);
+    cfg->lds_b = lds_for(cfg->corr);
     while (std::max(cfg->lds_a, cfg->lds_b) > kLdsLimit && cfg->kind == KIND_SLIDE && cfg->S > 8) {
         cfg->S /= 2;
         cfg->TB = kNW * cfg->S;
-        cfg->lds_a = tile_lds_bytes(cfg->conv, cfg->orient, cfg->TB, extra);
-        cfg->lds_b = tile_lds_bytes(cfg->corr, cfg->orient, cfg->TB, extra);
+        cfg->lds_a = lds_for(cfg->conv);
+        cfg->lds_b = lds_for(cfg->corr);
     }
     if (std::max(cfg->lds_a, cfg->lds_b) > kLdsLimit) {
         *why = "PSF extent too large for the LDS tile";
@@ -383,7 +396,6 @@ template <int O, int S, bool B>
 PhaseFn span_fn(int lmax) {
     switch (lmax) {
         case 1: return rlk::span_kernel<O, S, 1, kNW, B>;
-        case 2: return rlk::span_kernel<O, S, 2, kNW, B>;
         case 4: return rlk::span_kernel<O, S, 4, kNW, B>;
         case 8: return rlk::span_kernel<O, S, 8, kNW, B>;
         case 16: return rlk::span_kernel<O, S, 16, kNW, B>;
@@ -393,12 +405,18 @@ PhaseFn span_fn(int lmax) {
 
 template <int O, bool B>
 PhaseFn span_fn_s(int S, int lmax) {
-    return S == 16 ? span_fn<O, 16, B>(lmax) : span_fn<O, 8, B>(lmax);
+    switch (S) {
+        case 4: return span_fn<O, 4, B>(lmax);
+        case 8: return span_fn<O, 8, B>(lmax);
+        case 16: return span_fn<O, 16, B>(lmax);
+    }
+    return nullptr;
 }
 
 template <int O, bool B>
 PhaseFn slide_fn(int S) {
     switch (S) {
+        case 4: return rlk::slide_kernel<O, 4, kNW, B>;
         case 8: return rlk::slide_kernel<O, 8, kNW, B>;
         case 16: return rlk::slide_kernel<O, 16, kNW, B>;
         case 32: return rlk::slide_kernel<O, 32, kNW, B>;

@@ -375,12 +375,33 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
 }
 
 // ---------------------------------------------------------------------------------------
-// Span kernel: every PSF line is cut into pieces of at most LMAX taps (any weights).  Each
-// lane keeps a register window of S + LMAX - 1 source values per piece and forms S outputs
+// Span kernel: every PSF line is cut into pieces of at most LMAX taps (any weights).  Per
+// piece a lane loads a register window of S + len - 1 source values and forms S outputs
 // from it (register blocking: one LDS read per output per piece instead of one per tap).
-// Partial sums are per PSF line in float32; lines are combined with Kahan compensation
-// (kahan = 1) or plainly.  LMAX = 1 with the per-tap table is the DIRECT path.
+// The piece length selects, by a wavefront-uniform switch, a body with exactly len FMAs
+// per output, so short pieces cost no padding.  Partial sums are per PSF line in float32;
+// with compensation on (kahan = 1) lines go alternately into two accumulators added at
+// the end (cascade summation, one add per line), else into one.  LMAX = 1 with the per-tap
+// table is the DIRECT path.
 // ---------------------------------------------------------------------------------------
+template <int ORIENT, int S, int L>
+__device__ __forceinline__ void span_piece(const float* lds, const TileGeom<ORIENT>& g, int ia,
+                                           int ib, ConstFloatPtr wp, float (&part)[S]) {
+    float w[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) w[t] = wp[t];
+    float win[S + L - 1];
+#pragma unroll
+    for (int q = 0; q < S + L - 1; ++q) win[q] = lds[g.idx(ia, ib + q)];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        float a = part[s];
+#pragma unroll
+        for (int t = 0; t < L; ++t) a = fmaf(w[t], win[s + t], a);
+        part[s] = a;
+    }
+}
+
 template <int ORIENT, int S, int LMAX, int NW, bool PHASE_B>
 __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     extern __shared__ float lds[];
@@ -388,7 +409,7 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     int a0, b0;
     PhaseArgs p;
     if (!resolve<PHASE_B>(L, p, TA, TB, a0, b0)) return;
-    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, LMAX - 1);
+    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
     load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
@@ -398,50 +419,58 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int la = lane - p.lane_min;
     const int lb = wv * S - p.c_min;
-    float acc[S], comp[S], part[S];
+    float acc0[S], acc1[S], part[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) { acc[s] = 0.f; comp[s] = 0.f; part[s] = 0.f; }
-    const bool kahan = p.kahan != 0;
+    for (int s = 0; s < S; ++s) { acc0[s] = 0.f; acc1[s] = 0.f; part[s] = 0.f; }
+    const bool cascade = p.kahan != 0;
+    bool odd = false;
 
     const ConstSpanPtr spans = as_const(p.spans);
     const ConstFloatPtr wts = as_const(p.wts);
     for (int i = 0; i < p.n_spans; ++i) {
         const DevSpan sp = load_span(spans, i);
         const ConstFloatPtr wp = wts + sp.woff;
-        float wv_[LMAX];
-#pragma unroll
-        for (int t = 0; t < LMAX; ++t) wv_[t] = (t < sp.len) ? wp[t] : 0.f;
         const int ia = la + sp.lane_off, ib = lb + sp.c0;
-        float win[S + LMAX - 1];
-#pragma unroll
-        for (int q = 0; q < S + LMAX - 1; ++q) win[q] = lds[g.idx(ia, ib + q)];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            float a = part[s];
-#pragma unroll
-            for (int t = 0; t < LMAX; ++t) a = fmaf(wv_[t], win[s + t], a);
-            part[s] = a;
+        switch (sp.len) {
+#define RL_PIECE(n) \
+    case n:         \
+        if (n <= LMAX) span_piece<ORIENT, S, (n <= LMAX ? n : 1)>(lds, g, ia, ib, wp, part); \
+        break;
+            RL_PIECE(1) RL_PIECE(2) RL_PIECE(3) RL_PIECE(4) RL_PIECE(5) RL_PIECE(6)
+            RL_PIECE(7) RL_PIECE(8) RL_PIECE(9) RL_PIECE(10) RL_PIECE(11) RL_PIECE(12)
+            RL_PIECE(13) RL_PIECE(14) RL_PIECE(15) RL_PIECE(16)
+#undef RL_PIECE
+            default: break;
         }
         if (sp.row_end) {
-            if (kahan) {
+            if (cascade && odd) {
 #pragma unroll
-                for (int s = 0; s < S; ++s) { kahan_add(acc[s], comp[s], part[s]); part[s] = 0.f; }
+                for (int s = 0; s < S; ++s) { acc1[s] += part[s]; part[s] = 0.f; }
             } else {
 #pragma unroll
-                for (int s = 0; s < S; ++s) { acc[s] += part[s]; part[s] = 0.f; }
+                for (int s = 0; s < S; ++s) { acc0[s] += part[s]; part[s] = 0.f; }
             }
+            odd = !odd;
         }
     }
-    write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, acc, plan);
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc0[s] += acc1[s];
+    write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, acc0, plan);
 }
 
 // ---------------------------------------------------------------------------------------
 // Sliding kernel (generic box filter): every span is a run of equal weights.  Moving the
 // output one step along the strip adds the entering tap and removes the leaving tap of each
-// run, 2 operations per run per output.  The first output of the strip is seeded by the
-// full sum (per-run partials combined with Kahan); the per-step changes are combined in a
-// Kahan-compensated running sum (kahan = 1) or a plain one.
+// run, 2 operations per run per output.  The workgroup's NW wavefronts cover consecutive
+// strips of one tile row; only the tile's first output needs the full sum (the seed), and
+// its runs are split among the wavefronts.  Each wavefront forms the per-step changes of
+// its whole strip (including the step into it), a Kahan-compensated prefix of them, and
+// then its start value from the seed parts and the preceding wavefronts' totals, exchanged
+// through LDS.  kahan = 0 uses plain float32 sums instead.
 // ---------------------------------------------------------------------------------------
+template <int NW>
+__host__ __device__ constexpr int slide_scratch_floats() { return 4 * NW * 64; }
+
 template <int ORIENT, int S, int NW, bool PHASE_B>
 __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
     extern __shared__ float lds[];
@@ -458,48 +487,84 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int la = lane - p.lane_min;
-    const int lb = wv * S - p.c_min;
+    const int lb = wv * S - p.c_min;   // this wavefront's strip start
+    const int lb0 = -p.c_min;          // the tile's first output
     const bool kahan = p.kahan != 0;
     float seed = 0.f, seed_c = 0.f;
     float d[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) d[s] = 0.f;
-
     const ConstSpanPtr spans = as_const(p.spans);
     for (int i = 0; i < p.n_spans; ++i) {
         const DevSpan sp = load_span(spans, i);
         const float w = sp.w0;
         const int ia = la + sp.lane_off, ib = lb + sp.c0;
         const int len = sp.len;
-        // seed: the run's full sum at the strip's first output, four independent chains
-        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-        int q = 0;
-        for (; q + 4 <= len; q += 4) {
-            p0 += lds[g.idx(ia, ib + q)];
-            p1 += lds[g.idx(ia, ib + q + 1)];
-            p2 += lds[g.idx(ia, ib + q + 2)];
-            p3 += lds[g.idx(ia, ib + q + 3)];
+        if (i % NW == wv) {  // this wavefront's share of the seed
+            const int ib0 = lb0 + sp.c0;
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+            int q = 0;
+            for (; q + 4 <= len; q += 4) {
+                p0 += lds[g.idx(ia, ib0 + q)];
+                p1 += lds[g.idx(ia, ib0 + q + 1)];
+                p2 += lds[g.idx(ia, ib0 + q + 2)];
+                p3 += lds[g.idx(ia, ib0 + q + 3)];
+            }
+            for (; q < len; ++q) p0 += lds[g.idx(ia, ib0 + q)];
+            const float part = (p0 + p1) + (p2 + p3);
+            if (kahan) kahan_add(seed, seed_c, w * part);
+            else seed = fmaf(w, part, seed);
         }
-        for (; q < len; ++q) p0 += lds[g.idx(ia, ib + q)];
-        const float part = (p0 + p1) + (p2 + p3);
-        if (kahan) kahan_add(seed, seed_c, w * part);
-        else seed = fmaf(w, part, seed);
+        if (wv > 0) {
+            const float in = lds[g.idx(ia, ib + len - 1)];
+            const float outv = lds[g.idx(ia, ib - 1)];
+            d[0] = fmaf(w, in - outv, d[0]);
+        }
 #pragma unroll
         for (int s = 1; s < S; ++s) {
-            float in = lds[g.idx(ia, ib + s + len - 1)];
-            float outv = lds[g.idx(ia, ib + s - 1)];
+            const float in = lds[g.idx(ia, ib + s + len - 1)];
+            const float outv = lds[g.idx(ia, ib + s - 1)];
             d[s] = fmaf(w, in - outv, d[s]);
         }
     }
-    float out[S];
-    float run = seed, c = seed_c;
-    out[0] = run;
+    // prefix of the changes inside the strip (value P, compensation C: true sum = P - C)
+    float P[S], C[S];
+    {
+        float run = 0.f, c = 0.f;
 #pragma unroll
-    for (int s = 1; s < S; ++s) {
-        if (kahan) kahan_add(run, c, d[s]);
-        else run += d[s];
-        out[s] = run;
+        for (int s = 0; s < S; ++s) {
+            if (kahan) kahan_add(run, c, d[s]);
+            else run += d[s];
+            P[s] = run;
+            C[s] = c;
+        }
     }
+    // exchange seed parts and strip totals
+    float* xs = lds + g.ny * g.pitch;
+    xs[(0 * NW + wv) * 64 + lane] = seed;
+    xs[(1 * NW + wv) * 64 + lane] = seed_c;
+    xs[(2 * NW + wv) * 64 + lane] = P[S - 1];
+    xs[(3 * NW + wv) * 64 + lane] = C[S - 1];
+    __syncthreads();
+    float base = 0.f, bc = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const float part = xs[(0 * NW + w) * 64 + lane] - xs[(1 * NW + w) * 64 + lane];
+        if (kahan) kahan_add(base, bc, part);
+        else base += part;
+    }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wv) {
+            const float part = xs[(2 * NW + w) * 64 + lane] - xs[(3 * NW + w) * 64 + lane];
+            if (kahan) kahan_add(base, bc, part);
+            else base += part;
+        }
+    }
+    const float b_true = base - bc;
+    float out[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) out[s] = b_true + (P[s] - C[s]);
     write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, out, plan);
 }
 
