@@ -12,7 +12,20 @@ for each (copy u^K out).  Inputs are resident on the GPU before the timed region
 --mode sequential runs rl_iterate per job instead (the plain per-image method).
 
 Prints ONE JSON line.  Options: --gpus (must be 1), --steps, --warmup, --no-cpu-baseline,
---no-kernel-timing.
+--no-kernel-timing, --mode, --compare.
+
+--report N prints, instead of the benchmark line, one JSON report line for another
+configuration:
+  3  thinned RL, 2048x2048, disc r=16, Poisson 1000, 500 iterations, relative threshold
+     1e-4 held 5 iterations, reset and recompaction every 10: thinning-rate schedule,
+     omitted fraction, PSNR against the unthinned GPU run, both timings;
+  4  256 uneven images (sides log-uniform 256..2048, mixed PSFs, 100..300 iterations) in
+     one batch: throughput with compensated and plain float32 sums, and the error of both
+     against the FP64 oracle on the two cheapest jobs of each PSF class;
+  5  serving: Poisson arrivals of requests drawn from a pool (sides 128..4096, mixed
+     PSFs, 50..500 iterations, thinning on) at 70 % of the measured batched capacity:
+     p50/p99 latency and throughput of the continuous-batching server against the plain
+     one-at-a-time method on the same GPU.
 """
 import argparse
 import json
@@ -61,6 +74,8 @@ def main():
     ap.add_argument("--mode", choices=["batch", "sequential"], default="batch")
     ap.add_argument("--compare", action="store_true",
                     help="also time the other mode (reported as 'other_mode')")
+    ap.add_argument("--report", type=int, choices=[3, 4, 5], default=None)
+    ap.add_argument("--requests", type=int, default=48, help="--report 5: requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -76,6 +91,10 @@ def main():
 
     A.lib()  # fail loudly if the HIP library is not built
     dev = torch.device("cuda:0")
+    if args.report:
+        line = {3: report_thinned, 4: report_batched, 5: report_serving}[args.report](args, dev)
+        print(json.dumps(line), flush=True)
+        return
     jobs = synth.job_for_config(2)
     for j in jobs:
         j["iters"] = args.iters
@@ -218,6 +237,184 @@ def main():
         "other_mode": other,
     }
     print(json.dumps(line), flush=True)
+
+
+def _psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def report_thinned(args, dev):
+    import torch
+
+    import synth
+    from paper_1304_7211_amd.job import Job
+    job = synth.job_for_config(3)[0]
+    f = torch.from_numpy(job["f"]).to(dev)
+    K = job["iters"]
+    log(f"report 3: {job['f'].shape} disc r=16, K={K}, thin={job['thin']}")
+    res = {}
+    for name, thin in (("plain", None), ("thinned", job["thin"])):
+        j = Job(f, job["psf"], thin=thin)
+        j.iterate(2)
+        torch.cuda.synchronize()
+        j.close()
+        j = Job(f, job["psf"], thin=thin)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        j.iterate(K)
+        u, st = j.result(stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sched = j.thin_schedule() if thin else None
+        res[name] = dict(u=u.cpu().numpy(), t=dt, st=st, sched=sched, info=j.describe())
+        j.close()
+        log(f"report 3: {name} {dt * 1e3:.1f} ms")
+    N = job["f"].size
+    sched = np.array(res["thinned"]["sched"], dtype=np.float64) / N
+    omitted = 1.0 - sched.mean()
+    return {
+        "report": "thinned RL, config 3",
+        "workload": "2048x2048, disc r=16, Poisson peak 1000, 500 iterations, rel tau 1e-4, H=5, R=10, C=10",
+        "plain_ms": res["plain"]["t"] * 1e3,
+        "thinned_ms": res["thinned"]["t"] * 1e3,
+        "speedup": res["plain"]["t"] / res["thinned"]["t"],
+        "logical_px_it_per_s_thinned": N * K / res["thinned"]["t"],
+        "active_px_it_per_s_thinned": float(sched.sum() * N) / res["thinned"]["t"],
+        "px_it_per_s_plain": N * K / res["plain"]["t"],
+        "omitted_fraction": float(omitted),
+        "psnr_thinned_vs_plain_db": _psnr(res["thinned"]["u"], res["plain"]["u"]),
+        "active_fraction_at_k_5_15_25": [round(float(x), 4) for x in sched[5::10]],
+        "active_fraction_last_10": [round(float(x), 4) for x in sched[-10:]],
+        "flux_plain": res["plain"]["st"].flux,
+        "flux_thinned": res["thinned"]["st"].flux,
+    }
+
+
+def report_batched(args, dev):
+    import torch
+
+    import oracle
+    import synth
+    from paper_1304_7211_amd.job import BatchRunner, Job
+    t0 = time.perf_counter()
+    jobs = synth.job_for_config(4)
+    log(f"report 4: {len(jobs)} jobs generated in {time.perf_counter() - t0:.1f}s")
+    fs = [torch.from_numpy(j["f"]).to(dev) for j in jobs]
+    px_it = sum(j["f"].size * j["iters"] for j in jobs)
+    runner = BatchRunner(len(jobs))
+    out = {}
+    for kahan in (True, False):
+        js = [Job(f, j["psf"], kahan=kahan) for j, f in zip(jobs, fs)]
+        runner.iterate(js, [2] * len(js))  # warm the kernels
+        torch.cuda.synchronize()
+        for jb in js:
+            jb.close()
+        js = [Job(f, j["psf"], kahan=kahan) for j, f in zip(jobs, fs)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        runner.iterate(js, [j["iters"] for j in jobs])
+        us = [jb.result() for jb in js]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out[kahan] = dict(t=dt, u=us, paths=[jb.describe()["path"] for jb in js])
+        for jb in js:
+            jb.close()
+        log(f"report 4: kahan={kahan} {dt * 1e3:.1f} ms, {px_it / dt:.3g} px-it/s")
+    # FP64 oracle on the two cheapest jobs of each PSF class
+    cls = {}
+    for i, j in enumerate(jobs):
+        c = j["name"].split("-")[1]
+        cost = j["f"].size * j["iters"] * np.count_nonzero(j["psf"])
+        cls.setdefault(c, []).append((cost, i))
+    picked = [i for c in sorted(cls) for _, i in sorted(cls[c])[:2]]
+    o = oracle.Oracle()
+    errs = []
+    for i in picked:
+        j = jobs[i]
+        ref = o.rl(j["f"], j["psf"], j["iters"])
+        e = {}
+        for kahan in (True, False):
+            u = out[kahan]["u"][i].cpu().numpy().astype(np.float64)
+            e["compensated" if kahan else "plain"] = float(
+                np.max(np.abs(u - ref) / np.maximum(np.abs(ref), 1e-4)))
+        errs.append(dict(job=j["name"], shape=list(j["f"].shape), iters=j["iters"], **e))
+        log(f"report 4: {errs[-1]}")
+    return {
+        "report": "batched uneven jobs, config 4",
+        "workload": "256 images, sides log-uniform 256..2048, PSFs axis/oblique/disc/dense15, "
+                    "100..300 iterations, Poisson 255, one rl_iterate_batch call",
+        "px_it": px_it,
+        "compensated": {"ms": out[True]["t"] * 1e3, "px_it_per_s": px_it / out[True]["t"]},
+        "plain_sums": {"ms": out[False]["t"] * 1e3, "px_it_per_s": px_it / out[False]["t"]},
+        "max_rel_err_vs_fp64": {
+            "compensated": max(e["compensated"] for e in errs),
+            "plain": max(e["plain"] for e in errs)},
+        "checked_jobs": errs,
+    }
+
+
+def report_serving(args, dev):
+    import torch
+
+    import synth
+    from synth.configs import log_uniform_side, random_psf
+    from paper_1304_7211_amd.serve import (Request, Server, latency_report, run_stream,
+                                           serve_plain)
+    c = synth.CONFIGS[5]
+    rng = np.random.default_rng(c["seed"])
+    thin = dict(synth.CONFIGS[3]["thin"])
+    pool = []
+    t0 = time.perf_counter()
+    for i in range(24):
+        H = log_uniform_side(rng, c["side_lo"], c["side_hi"])
+        W = log_uniform_side(rng, c["side_lo"], c["side_hi"])
+        _, h = random_psf(rng)
+        K = int(rng.integers(c["K_lo"], c["K_hi"] + 1))
+        f = synth.observe(synth.latent_image(H, W, 500 + i), h, "poisson", 500 + i)
+        pool.append((f, h, K))
+    log(f"report 5: pool of {len(pool)} requests generated in {time.perf_counter() - t0:.1f}s")
+    pool_dev = [(torch.from_numpy(f).to(dev), h, K) for f, h, K in pool]
+    budget = int(0.5 * torch.cuda.mem_get_info(dev)[0])
+
+    def make(n, arrivals):
+        return [Request(i, pool_dev[i % len(pool)][0], pool_dev[i % len(pool)][1],
+                        pool_dev[i % len(pool)][2], thin=thin, arrival=float(a))
+                for i, a in enumerate(arrivals)]
+
+    # capacity: everything submitted at once
+    warm = Server(budget, max_slots=64, chunk=10)
+    run_stream(make(len(pool), [0.0] * len(pool)), warm)
+    srv = Server(budget, max_slots=64, chunk=10)
+    reqs = make(len(pool), [0.0] * len(pool))
+    dt = run_stream(reqs, srv)
+    capacity = len(pool) / dt
+    px_it_pool = sum(f.size * K for f, _, K in pool)
+    log(f"report 5: batched capacity {capacity:.1f} req/s ({px_it_pool / dt:.3g} px-it/s)")
+    qps = 0.7 * capacity
+    n = args.requests
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n))
+    reqs = make(n, arrivals)
+    srv = Server(budget, max_slots=64, chunk=10)
+    dt_c = run_stream(reqs, srv)
+    rep_c = latency_report(reqs)
+    base = make(n, arrivals)
+    dt_p = serve_plain(base)
+    rep_p = latency_report(base)
+    same = all(torch.equal(a.result, b.result) for a, b in zip(reqs, base))
+    px_it = sum(pool[i % len(pool)][0].size * pool[i % len(pool)][2] for i in range(n))
+    log(f"report 5: continuous {rep_c}, plain {rep_p}, identical={same}")
+    return {
+        "report": "serving, config 5",
+        "workload": f"{n} requests from a pool of {len(pool)} (sides 128..4096, mixed PSFs, "
+                    "50..500 iterations, thinning rel 1e-4 H5 R10 C10), Poisson arrivals",
+        "qps": qps,
+        "batched_capacity_req_per_s": capacity,
+        "continuous": dict(latency=rep_c, wall_s=dt_c, px_it_per_s=px_it / dt_c,
+                           peak_slots=srv.ctl.peak_slots),
+        "plain_per_image": dict(latency=rep_p, wall_s=dt_p, px_it_per_s=px_it / dt_p),
+        "results_identical": bool(same),
+    }
 
 
 def cpu_baseline(jobs):

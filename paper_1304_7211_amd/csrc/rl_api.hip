@@ -55,7 +55,7 @@ struct Config {
 
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
-        bcounts, boffs, ctr, sched, red, red_i, args, prefix, total;
+        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, total;
 };
 
 // counters block (int64 slots)
@@ -299,6 +299,7 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
         L.bcounts = take(thin_blocks(N) * 4);
         L.boffs = take(thin_blocks(N) * 4);
         L.sched = take(rlk::SCHED_RING * 8);
+        L.act = take(2 * rlk::ACT_SLOTS * 4);
     }
     L.ctr = take(C_COUNT * 8);
     L.args = take(2 * sizeof(PhaseArgs));
@@ -336,6 +337,7 @@ struct rl_job {
     char* ws;
     int64_t k;
     bool list_valid;
+    bool pending_finalize;  // thinned: the active count of iteration k - 1 is not folded yet
     bool live;
     std::vector<DevSpan> h_conv, h_corr;
     std::vector<float> h_conv_w, h_corr_w;
@@ -492,6 +494,7 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
         a.tau = j->p.thin.tau;
         a.sched = j->at<int64_t>(j->L.sched);
         a.active_total = j->at<int64_t>(j->L.ctr) + C_ACTIVE_TOTAL;
+        a.act_part = j->at<int32_t>(j->L.act);
         a.tile_list = j->at<int32_t>(j->L.tlist);
         a.tile_count = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
     }
@@ -581,7 +584,20 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
         st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lb), nbn);
         if (st) return st;
         j->k += 1;
+        if (thin) j->pending_finalize = true;
     }
+    return RL_OK;
+}
+
+// Fold the active count of the last thinned iteration into the schedule (the next
+// iteration's phase A would otherwise do it).
+rl_status finalize_thin(rl_job* j, hipStream_t s) {
+    if (!j->pending_finalize || j->p.thin.mode == RL_THIN_OFF || j->k == 0) return RL_OK;
+    rl_status st = dev_err(launch("thin_finalize", rlk::thin_finalize_kernel, dim3(1), dim3(64), 0, s,
+                                  j->at<int32_t>(j->L.act), j->at<int64_t>(j->L.sched),
+                                  j->at<int64_t>(j->L.ctr) + C_ACTIVE_TOTAL, j->k - 1), "finalize");
+    if (st) return st;
+    j->pending_finalize = false;
     return RL_OK;
 }
 
@@ -677,6 +693,7 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     j->psf = c;
     j->k = 0;
     j->list_valid = false;
+    j->pending_finalize = false;
     j->live = true;
     st = choose_config(p, c, &j->cfg, &why);
     if (st) { delete j; return st; }
@@ -717,6 +734,7 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(N / 4 + 1)), dim3(256), 0, s, j->at<uint32_t>(j->L.cnt), 0u, (N + 3) / 4), "zero cnt"))) { delete j; return st; }
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(nt)), dim3(256), 0, s, j->at<uint32_t>(j->L.tflag), 0u, nt), "zero tflag"))) { delete j; return st; }
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(rlk::SCHED_RING * 2)), dim3(256), 0, s, j->at<uint32_t>(j->L.sched), 0u, (int64_t)rlk::SCHED_RING * 2), "zero ring"))) { delete j; return st; }
+        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(2), dim3(256), 0, s, j->at<uint32_t>(j->L.act), 0u, (int64_t)2 * rlk::ACT_SLOTS), "zero act"))) { delete j; return st; }
     }
     if ((st = dev_err(launch("check_f", rlk::check_f_kernel, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s,
                              (const float*)j->at<float>(j->L.f), N, reinterpret_cast<int32_t*>(j->at<int64_t>(j->L.ctr) + C_F_INVALID)), "check f"))) { delete j; return st; }
@@ -742,6 +760,7 @@ rl_status rl_result(rl_job* j, float* u_out, rl_stats* st) {
     if (!st) return RL_OK;
     int64_t* ctr = j->at<int64_t>(j->L.ctr);
     const bool thin = j->p.thin.mode != RL_THIN_OFF;
+    if (thin && (rs = finalize_thin(j, s))) return rs;
     if ((rs = dev_err(launch("reduce_sum", rlk::reduce_sum_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
                              (const float*)j->at<float>(j->L.u), j->N, j->at<double>(j->L.red)), "reduce"))) return rs;
     if (thin) {
@@ -931,7 +950,10 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         if ((st = dev_err(hipEventRecord(g_join[q], g_side[q]), "join"))) return st;
         if ((st = dev_err(hipStreamWaitEvent(s, g_join[q], 0), "join wait"))) return st;
     }
-    for (int i : tiled) jobs[i]->k += n_iter[i];
+    for (int i : tiled) {
+        jobs[i]->k += n_iter[i];
+        if (n_iter[i] > 0 && jobs[i]->p.thin.mode != RL_THIN_OFF) jobs[i]->pending_finalize = true;
+    }
     return RL_OK;
 }
 
@@ -965,8 +987,8 @@ rl_status rl_set_state(rl_job* j, const float* u, const float* r, const uint8_t*
     j->k = k;
     j->list_valid = false;
     if (j->p.thin.mode != RL_THIN_OFF) {
-        int64_t* slot = j->at<int64_t>(j->L.sched) + (k % rlk::SCHED_RING);
-        if ((st = dev_err(launch("ring_zero", rlk::set_i64_kernel, dim3(1), dim3(1), 0, s, slot, (int64_t)0), "ring"))) return st;
+        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(2), dim3(256), 0, s, j->at<uint32_t>(j->L.act), 0u, (int64_t)2 * rlk::ACT_SLOTS), "zero act"))) return st;
+        j->pending_finalize = false;
     }
     return RL_OK;
 }
@@ -994,6 +1016,8 @@ rl_status rl_thin_schedule(rl_job* j, int64_t* out, int32_t cap, int32_t* n) {
     if (!j || !n) return RL_E_INVAL;
     if (!j->live || j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
     std::vector<int64_t> ring(rlk::SCHED_RING);
+    rl_status fs = finalize_thin(j, j->stream);
+    if (fs) return fs;
     hipError_t e = hipMemcpyAsync(ring.data(), j->at<int64_t>(j->L.sched), ring.size() * 8, hipMemcpyDeviceToHost, j->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(j->stream);
     rl_status st = dev_err(e, "schedule");

@@ -25,6 +25,7 @@ constexpr int THIN_OFF = 0;
 constexpr int THIN_ABS = 1;
 constexpr int THIN_REL = 2;
 constexpr int SCHED_RING = 4096;  // per-iteration active-count ring
+constexpr int ACT_SLOTS = 256;     // spread slots for the per-iteration active count
 
 // device copy of rl::Span (same layout)
 struct DevSpan {
@@ -107,6 +108,7 @@ struct PhaseArgs {
     int32_t pad0;
     int64_t* sched;                // active-count ring (thinning)
     int64_t* active_total;         // running sum of |A_k|
+    int32_t* act_part;             // 2 banks x ACT_SLOTS partial active counts
     int64_t k;                     // base iteration index (plus LaunchArgs::kb)
 };
 
@@ -132,7 +134,7 @@ __device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
     p.tile_list = t->tile_list; p.tile_count = t->tile_count;
     p.thin_mode = t->thin_mode; p.hyst = t->hyst; p.reset_period = t->reset_period;
     p.full = t->full; p.tau = t->tau; p.pad0 = 0;
-    p.sched = t->sched; p.active_total = t->active_total; p.k = t->k;
+    p.sched = t->sched; p.active_total = t->active_total; p.act_part = t->act_part; p.k = t->k;
     return p;
 }
 
@@ -146,11 +148,38 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return start + idx;
 }
 
+// Add the spread partial active counts of iteration k (bank k & 1) to its schedule-ring
+// slot and to the running total, and clear the bank (folding an already folded bank adds
+// 0).  If k_next >= 0, also clear the ring slot of iteration k_next.  One wavefront.
+__device__ __forceinline__ void thin_finalize_wave(int32_t* act_part, int64_t* sched,
+                                                   int64_t* active_total, int64_t k,
+                                                   int64_t k_next) {
+    const int lane = threadIdx.x & 63;
+    int64_t v = 0;
+    if (k >= 0) {
+        int32_t* bank = act_part + (k & 1) * ACT_SLOTS;
+#pragma unroll
+        for (int q = 0; q < ACT_SLOTS / 64; ++q) {
+            v += bank[lane + 64 * q];
+            bank[lane + 64 * q] = 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    }
+    if (lane == 0) {
+        if (k >= 0) {
+            sched[k % SCHED_RING] += v;
+            *active_total += v;
+        }
+        if (k_next >= 0) sched[k_next % SCHED_RING] = 0;
+    }
+}
+
 // Find this workgroup's job and tile.  Returns false if the workgroup has no tile (thinned
 // steps launch one workgroup per tile of the grid and use only as many as the list has).
 // Thinned mode: iteration k is full when k == 0 or k % R == 0; on other steps the tiles
-// come from the compacted list.  The first workgroup of a job in phase A also clears the
-// active-count ring slot of iteration k + 1 (phase B of iteration k adds into slot k).
+// come from the compacted list.  The first wavefront of a job's first workgroup in phase A
+// folds the active count of iteration k - 1 into the schedule ring (phase B of iteration
+// k - 1 spread it over ACT_SLOTS counters, see add_active).
 template <bool PHASE_B>
 __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int TA, int TB,
                                         int& a0, int& b0) {
@@ -170,13 +199,17 @@ __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int T
     if (p.cnt) {
         p.full = (p.k == 0 || (p.reset_period > 0 && p.k % p.reset_period == 0)) ? 1 : 0;
         use_list = !p.full;
-        if (!PHASE_B && local == 0 && threadIdx.x == 0) p.sched[(p.k + 1) % SCHED_RING] = 0;
+        if (!PHASE_B && local == 0 && threadIdx.x < 64)
+            thin_finalize_wave(p.act_part, p.sched, p.active_total, p.k - 1, p.k);
     } else {
         p.full = 1;
     }
     const int n = use_list ? (int)*p.tile_count : p.tiles_a * p.tiles_b;
-    const int slot = (L.n_jobs == 1 && !use_list && n == nb_job) ? xcd_tile(local, nb_job) : local;
-    if (slot >= n) return false;
+    // XCD-aware order (single-job launches): workgroups local < n form a permutation of the
+    // n tiles (or list entries, which are ascending tile ids) with one contiguous range per
+    // XCD; workgroups past n (thinned steps with a short list) have no tile
+    if (local >= n) return false;
+    const int slot = (L.n_jobs == 1) ? xcd_tile(local, n) : local;
     const int t = use_list ? p.tile_list[slot] : slot;
     a0 = (t % p.tiles_a) * TA;
     b0 = (t / p.tiles_a) * TB;
@@ -258,13 +291,15 @@ __device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, 
 }
 
 // Per-wave sum of an int and one atomic add (thinned mode active counts).
+// Each wavefront adds its count into one of ACT_SLOTS counters of bank k & 1 (spread, so
+// thousands of wavefronts do not serialise on one address); integer adds, so the total
+// does not depend on their order.
 __device__ __forceinline__ void add_active(const PhaseArgs& p, int n_active) {
     if (!p.cnt) return;
     for (int off = 32; off > 0; off >>= 1) n_active += __shfl_xor(n_active, off);
     if ((threadIdx.x & 63) == 0 && n_active) {
-        atomicAdd((unsigned long long*)&p.sched[p.k % SCHED_RING],
-                  (unsigned long long)n_active);
-        atomicAdd((unsigned long long*)p.active_total, (unsigned long long)n_active);
+        const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % ACT_SLOTS);
+        atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + slot], n_active);
     }
 }
 
@@ -658,7 +693,10 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
     const int tpl = 64 * a.wpl;                               // threads per line
     const int j = threadIdx.x / tpl;                          // line within the workgroup
     const int t = threadIdx.x % tpl;                          // segment within the line
-    const int line = blockIdx.x * a.lines_per_wg + j;
+    // neighbouring lines share cache lines (column lines especially): give each XCD a
+    // contiguous range of workgroups so those lines are fetched once per XCD
+    const int wg = xcd_tile(blockIdx.x, gridDim.x);
+    const int line = wg * a.lines_per_wg + j;
     const bool live = (j < a.lines_per_wg) && (line < m);
     const int halo = a.halo;
     float* ul = lds + (size_t)j * 2 * a.line_words;
@@ -927,5 +965,10 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* dst, uint32_t v
 }
 
 __global__ void set_i64_kernel(int64_t* dst, int64_t v) { *dst = v; }
+
+__global__ __launch_bounds__(64) void thin_finalize_kernel(int32_t* act_part, int64_t* sched,
+                                                           int64_t* active_total, int64_t k) {
+    thin_finalize_wave(act_part, sched, active_total, k, -1);
+}
 
 }  // namespace rlk
