@@ -68,6 +68,9 @@ typedef int32_t rl_status;
 #define RL_SCHED_TWO_PASS 1 /* conv+ratio kernel, then corr+update kernel, per iteration   */
 #define RL_SCHED_RESIDENT 2 /* BOX_AXIS only: independent lines held on chip for all
                                iterations of one rl_iterate call                           */
+#define RL_SCHED_FUSED 3    /* one kernel per iteration: conv, ratio, corr and update on an
+                               LDS tile with a double halo (u double-buffered); plain jobs
+                               with height, width >= 64 and PSF extents <= 63 only         */
 
 /* thinning (Section 4) */
 #define RL_THIN_OFF 0

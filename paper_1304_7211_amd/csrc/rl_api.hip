@@ -33,7 +33,7 @@ constexpr int kNW = 4;  // wavefronts per workgroup in the tiled kernels
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2 };
+enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3 };
 
 // ---- kernel timing registry -----------------------------------------------------------
 struct TimedLaunch {
@@ -55,7 +55,7 @@ struct Config {
 
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
-        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, total;
+        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, total;
 };
 
 // counters block (int64 slots)
@@ -130,7 +130,35 @@ rl_status choose_config(const rl_params* p, const rl::CompiledPsf& c, Config* cf
     }
     cfg->path = path;
     int sched = p->schedule;
-    if (sched < RL_SCHED_AUTO || sched > RL_SCHED_RESIDENT) { *why = "unknown schedule"; return RL_E_INVAL; }
+    if (sched < RL_SCHED_AUTO || sched > RL_SCHED_FUSED) { *why = "unknown schedule"; return RL_E_INVAL; }
+    if (sched == RL_SCHED_FUSED) {
+        if (thin) { *why = "the fused schedule serves plain RL"; return RL_E_UNSUPPORTED; }
+        if (H < 64 || W < 64) { *why = "the fused schedule needs images of at least 64 x 64"; return RL_E_UNSUPPORTED; }
+        cfg->sched = RL_SCHED_FUSED;
+        cfg->kind = KIND_FUSED;
+        cfg->orient = rlk::ORIENT_ROWS;
+        cfg->S = 8;
+        cfg->TA = 64;
+        cfg->TB = kNW * cfg->S;
+        cfg->lmax = 16;
+        rl::Orient o = rl::Orient::Rows;
+        cfg->conv = rl::build_op_table(p->psf, p->psf_h, p->psf_w, false, o, false, 16);
+        cfg->corr = rl::build_op_table(p->psf, p->psf_h, p->psf_w, true, o, false, 16);
+        const rl::OpTable &v = cfg->conv, &c2 = cfg->corr;
+        const int ext[8] = {v.lane_min, v.lane_max, v.c_min, v.c_max, c2.lane_min, c2.lane_max, c2.c_min, c2.c_max};
+        for (int e : ext)
+            if (e < -63 || e > 63) { *why = "PSF extent too large for the fused schedule"; return RL_E_UNSUPPORTED; }
+        if (std::abs(c2.lane_min + c2.lane_max) > cfg->TA || std::abs(c2.c_min + c2.c_max) > cfg->TB) {
+            *why = "PSF too one-sided for the fused tile"; return RL_E_UNSUPPORTED;
+        }
+        const int RA = cfg->TA + c2.lane_max - c2.lane_min, RB = cfg->TB + c2.c_max - c2.c_min;
+        const int UA = RA + v.lane_max - v.lane_min, UB = RB + v.c_max - v.c_min;
+        cfg->lds_a = ((size_t)UA * (UB | 1) + (size_t)RA * (RB | 1) + cfg->S) * sizeof(float);
+        if (cfg->lds_a > kLdsLimit) { *why = "PSF extent too large for the fused LDS tile"; return RL_E_UNSUPPORTED; }
+        cfg->tiles_a = (H + cfg->TA - 1) / cfg->TA;
+        cfg->tiles_b = (W + cfg->TB - 1) / cfg->TB;
+        return RL_OK;
+    }
     const int box_orient = c.box_orient == rl::Orient::Rows ? rlk::ORIENT_ROWS : rlk::ORIENT_COLS;
     if (path == RL_PATH_BOX_AXIS && !thin && sched != RL_SCHED_TWO_PASS) {
         int n = box_orient == rlk::ORIENT_ROWS ? W : H;
@@ -303,6 +331,8 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     }
     L.ctr = take(C_COUNT * 8);
     L.args = take(2 * sizeof(PhaseArgs));
+    L.u2 = cfg.kind == KIND_FUSED ? take(N * 4) : 0;
+    L.fargs = take(sizeof(rlk::FusedArgs));
     L.prefix = take(2 * sizeof(int32_t));
     L.red = take(rlk::RED_BLOCKS * 8);
     L.red_i = take(rlk::RED_BLOCKS * 8);
@@ -343,6 +373,12 @@ struct rl_job {
     std::vector<float> h_conv_w, h_corr_w;
     PhaseArgs h_args[2];
     int32_t h_prefix[2];
+    rlk::FusedArgs h_fargs;
+    // the plane holding u^k: the fused schedule alternates between u and u2
+    float* cur_u() const {
+        return (cfg.kind == KIND_FUSED && (k & 1)) ? reinterpret_cast<float*>(ws + L.u2)
+                                                   : reinterpret_cast<float*>(ws + L.u);
+    }
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -561,6 +597,17 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
         j->k += n;
         return RL_OK;
     }
+    if (c.kind == KIND_FUSED) {
+        const rlk::FusedArgs* table = j->at<rlk::FusedArgs>(j->L.fargs);
+        for (int i = 0; i < n; ++i) {
+            rl_status st = dev_err(launch("fused_iteration", rlk::fused_kernel<8, 16, kNW>,
+                                          dim3(c.tiles_a * c.tiles_b), dim3(kNW * 64), c.lds_a,
+                                          s, table, (int64_t)j->k), "fused");
+            if (st) return st;
+            j->k += 1;
+        }
+        return RL_OK;
+    }
     const bool thin = j->p.thin.mode != RL_THIN_OFF;
     const int ntiles = c.tiles_a * c.tiles_b;
     PhaseFn fa = phase_fn(c, false), fb = phase_fn(c, true);
@@ -714,7 +761,32 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.conv_w), j->h_conv_w.data(), j->h_conv_w.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_w), j->h_corr_w.data(), j->h_corr_w.size() * 4, hipMemcpyHostToDevice, s);
     if ((st = dev_err(e, "upload PSF"))) { delete j; return st; }
-    if (j->cfg.kind != KIND_RESIDENT) {
+    if (j->cfg.kind == KIND_FUSED) {
+        rlk::FusedArgs& a = j->h_fargs;
+        a = rlk::FusedArgs{};
+        a.H = j->H;
+        a.W = j->W;
+        a.bc = p->boundary;
+        a.kahan = p->kahan;
+        a.f = j->at<float>(j->L.f);
+        a.u0 = j->at<float>(j->L.u);
+        a.u1 = j->at<float>(j->L.u2);
+        a.cspans = j->at<DevSpan>(j->L.conv_spans);
+        a.cwts = j->at<float>(j->L.conv_w);
+        a.rspans = j->at<DevSpan>(j->L.corr_spans);
+        a.rwts = j->at<float>(j->L.corr_w);
+        a.n_cspans = (int32_t)j->cfg.conv.spans.size();
+        a.n_rspans = (int32_t)j->cfg.corr.spans.size();
+        a.vl_min = j->cfg.conv.lane_min; a.vl_max = j->cfg.conv.lane_max;
+        a.vc_min = j->cfg.conv.c_min; a.vc_max = j->cfg.conv.c_max;
+        a.cl_min = j->cfg.corr.lane_min; a.cl_max = j->cfg.corr.lane_max;
+        a.cc_min = j->cfg.corr.c_min; a.cc_max = j->cfg.corr.c_max;
+        a.tiles_a = j->cfg.tiles_a;
+        a.tiles_b = j->cfg.tiles_b;
+        a.k = 0;
+        e = hipMemcpyAsync(j->at<void>(j->L.fargs), &j->h_fargs, sizeof j->h_fargs, hipMemcpyHostToDevice, s);
+        if ((st = dev_err(e, "upload fused args"))) { delete j; return st; }
+    } else if (j->cfg.kind != KIND_RESIDENT) {
         j->h_args[0] = phase_args(j, false, 0);
         j->h_args[1] = phase_args(j, true, 0);
         j->h_prefix[0] = 0;
@@ -755,14 +827,14 @@ rl_status rl_result(rl_job* j, float* u_out, rl_stats* st) {
     hipStream_t s = j->stream;
     rl_status rs;
     if (u_out) {
-        if ((rs = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(grid_for(j->N)), dim3(256), 0, s, u_out, (const float*)j->at<float>(j->L.u), j->N), "copy u"))) return rs;
+        if ((rs = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(grid_for(j->N)), dim3(256), 0, s, u_out, (const float*)j->cur_u(), j->N), "copy u"))) return rs;
     }
     if (!st) return RL_OK;
     int64_t* ctr = j->at<int64_t>(j->L.ctr);
     const bool thin = j->p.thin.mode != RL_THIN_OFF;
     if (thin && (rs = finalize_thin(j, s))) return rs;
     if ((rs = dev_err(launch("reduce_sum", rlk::reduce_sum_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
-                             (const float*)j->at<float>(j->L.u), j->N, j->at<double>(j->L.red)), "reduce"))) return rs;
+                             (const float*)j->cur_u(), j->N, j->at<double>(j->L.red)), "reduce"))) return rs;
     if (thin) {
         if ((rs = dev_err(launch("count_active", rlk::count_active_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
                                  (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N, (int)j->p.thin.hysteresis, j->at<int64_t>(j->L.red_i)), "count"))) return rs;
@@ -826,7 +898,7 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     rl_status st;
     std::vector<int> tiled, resident;
     for (int32_t i = 0; i < n_jobs; ++i) {
-        if (jobs[i]->cfg.kind == KIND_RESIDENT) resident.push_back(i);
+        if (jobs[i]->cfg.kind == KIND_RESIDENT || jobs[i]->cfg.kind == KIND_FUSED) resident.push_back(i);
         else tiled.push_back(i);
     }
     if (tiled.empty() && resident.empty()) return RL_OK;
@@ -907,7 +979,8 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     for (int q = 0; q < n_streams; ++q)
         if ((st = dev_err(hipStreamWaitEvent(g_side[q], g_fork, 0), "fork wait"))) return st;
     auto stream_of_group = [&](size_t gi) { return g_side[gi % n_streams]; };
-    // jobs on the resident schedule run all their iterations in one launch each
+    // jobs on the resident schedule run all their iterations in one launch each; fused
+    // jobs one launch per iteration, on the same side stream
     for (int i : resident) {
         rl_job* j = jobs[i];
         hipStream_t keep = j->stream;
@@ -963,7 +1036,7 @@ rl_status rl_get_state(rl_job* j, float* u, float* r, uint8_t* cnt, int64_t* k_o
     hipStream_t s = j->stream;
     unsigned g = grid_for(j->N);
     rl_status st;
-    if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, u, (const float*)j->at<float>(j->L.u), j->N), "get u"))) return st;
+    if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, u, (const float*)j->cur_u(), j->N), "get u"))) return st;
     if (r && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, r, (const float*)j->at<float>(j->L.r), j->N), "get r"))) return st;
     if (cnt) {
         if (j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
@@ -981,7 +1054,8 @@ rl_status rl_set_state(rl_job* j, const float* u, const float* r, const uint8_t*
     hipStream_t s = j->stream;
     unsigned g = grid_for(j->N);
     rl_status st;
-    if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.u), u, j->N), "set u"))) return st;
+    j->k = k;  // selects the plane that holds u^k (fused schedule)
+    if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->cur_u(), u, j->N), "set u"))) return st;
     if (r && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.r), r, j->N), "set r"))) return st;
     if (cnt && (st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, j->at<uint8_t>(j->L.cnt), cnt, j->N), "set cnt"))) return st;
     j->k = k;

@@ -604,6 +604,178 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Fused iteration kernel: conv -> ratio -> corr -> update in one launch (ORIENT_ROWS,
+// lanes are image rows).  A workgroup owns a 64 x (NW*S) output tile.  It loads u^k for the
+// tile plus both halos (conv halo around the corr halo) into LDS, forms r = f / (u^k * h)
+// for the tile plus the corr halo into a second LDS tile, copies the boundary continuation
+// into the out-of-image part of that r tile, then correlates and writes
+// u^{k+1} = u^k . (h^* * r) into the other u plane (neighbouring workgroups still read
+// u^k).  Tiles at the bottom/right edge are shifted inwards so that every tile lies inside
+// the image; the folded positions its r halo needs are then inside its own r tile (needs
+// H >= 64, W >= NW*S and halos <= 63).  Overlapping tiles compute identical values.
+// ---------------------------------------------------------------------------------------
+struct FusedArgs {
+    int32_t H, W, bc, kahan;
+    const float* f;
+    float* u0;            // u^k for even k, u^{k+1} for odd k
+    float* u1;            // the other plane
+    const DevSpan* cspans;  // conv table (forward, mirrored taps)
+    const float* cwts;
+    const DevSpan* rspans;  // corr table (adjoint)
+    const float* rwts;
+    int32_t n_cspans, n_rspans;
+    int32_t vl_min, vl_max, vc_min, vc_max;  // conv extents (lane, strip)
+    int32_t cl_min, cl_max, cc_min, cc_max;  // corr extents
+    int32_t tiles_a, tiles_b;
+    int64_t k;
+};
+
+typedef const __attribute__((address_space(4))) FusedArgs* ConstFusedPtr;
+
+__device__ __forceinline__ FusedArgs load_fused(ConstFusedPtr t) {
+    FusedArgs a;
+    a.H = t->H; a.W = t->W; a.bc = t->bc; a.kahan = t->kahan;
+    a.f = t->f; a.u0 = t->u0; a.u1 = t->u1;
+    a.cspans = t->cspans; a.cwts = t->cwts; a.rspans = t->rspans; a.rwts = t->rwts;
+    a.n_cspans = t->n_cspans; a.n_rspans = t->n_rspans;
+    a.vl_min = t->vl_min; a.vl_max = t->vl_max; a.vc_min = t->vc_min; a.vc_max = t->vc_max;
+    a.cl_min = t->cl_min; a.cl_max = t->cl_max; a.cc_min = t->cc_min; a.cc_max = t->cc_max;
+    a.tiles_a = t->tiles_a; a.tiles_b = t->tiles_b; a.k = t->k;
+    return a;
+}
+
+// S outputs of one strip: out[s] = sum over the table of w * src(a + lane_off, b + s + c0),
+// src an LDS tile of the given pitch, (a, b) already relative to the tile origin.
+template <int S, int LMAX>
+__device__ __forceinline__ void strip_sum(const float* src, int pitch, int a, int b,
+                                          ConstSpanPtr spans, ConstFloatPtr wts, int n,
+                                          bool cascade, float (&out)[S]) {
+    TileGeom<ORIENT_ROWS> g;
+    g.pitch = pitch;
+    float acc1[S], part[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) { out[s] = 0.f; acc1[s] = 0.f; part[s] = 0.f; }
+    bool odd = false;
+    for (int i = 0; i < n; ++i) {
+        const DevSpan sp = load_span(spans, i);
+        const ConstFloatPtr wp = wts + sp.woff;
+        const int ia = a + sp.lane_off, ib = b + sp.c0;
+        switch (sp.len) {
+#define RL_PIECE(m) \
+    case m:         \
+        if (m <= LMAX) span_piece<ORIENT_ROWS, S, (m <= LMAX ? m : 1)>(src, g, ia, ib, wp, part); \
+        break;
+            RL_PIECE(1) RL_PIECE(2) RL_PIECE(3) RL_PIECE(4) RL_PIECE(5) RL_PIECE(6)
+            RL_PIECE(7) RL_PIECE(8) RL_PIECE(9) RL_PIECE(10) RL_PIECE(11) RL_PIECE(12)
+            RL_PIECE(13) RL_PIECE(14) RL_PIECE(15) RL_PIECE(16)
+#undef RL_PIECE
+            default: break;
+        }
+        if (sp.row_end) {
+            if (cascade && odd) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) { acc1[s] += part[s]; part[s] = 0.f; }
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; ++s) { out[s] += part[s]; part[s] = 0.f; }
+            }
+            odd = !odd;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) out[s] += acc1[s];
+}
+
+template <int S, int LMAX, int NW>
+__global__ __launch_bounds__(NW * 64) void fused_kernel(const FusedArgs* table, int64_t kb) {
+    extern __shared__ float lds[];
+    constexpr int TA = 64, TB = NW * S;
+    const FusedArgs p = load_fused((ConstFusedPtr)table);
+    const int64_t k = p.k + kb;
+    const float* u_in = (k & 1) ? p.u1 : p.u0;
+    float* u_out = (k & 1) ? p.u0 : p.u1;
+    const int nt = p.tiles_a * p.tiles_b;
+    if ((int)blockIdx.x >= nt) return;
+    const int t = xcd_tile(blockIdx.x, nt);
+    const int a0 = min((t % p.tiles_a) * TA, p.H - TA);
+    const int b0 = min((t / p.tiles_a) * TB, p.W - TB);
+    // r region (tile + corr halo), u region (r region + conv halo), relative origins
+    const int RA = TA + p.cl_max - p.cl_min, RB = TB + p.cc_max - p.cc_min;
+    const int ra0 = a0 + p.cl_min, rb0 = b0 + p.cc_min;
+    const int UA = RA + p.vl_max - p.vl_min, UB = RB + p.vc_max - p.vc_min;
+    const int ua0 = ra0 + p.vl_min, ub0 = rb0 + p.vc_min;
+    const int upitch = UB | 1, rpitch = RB | 1;
+    float* ut = lds;
+    float* rt = lds + UA * upitch;
+    load_tile(ut, u_in, p.H, p.W, p.bc, ua0, ub0, UA, UB, upitch);
+    lds_dma_wait();
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool cascade = p.kahan != 0;
+    const ConstSpanPtr cs = as_const(p.cspans), rs = as_const(p.rspans);
+    const ConstFloatPtr cw = as_const(p.cwts), rw = as_const(p.rwts);
+    // 1. r = f / (u*h) on the in-image part of the r region
+    const int blocks = (RA + 63) >> 6, strips = (RB + S - 1) / S;
+    for (int it = wv; it < blocks * strips; it += NW) {
+        const int blk = it / strips, st = it - blk * strips;
+        const int ra = blk * 64 + lane, rb = st * S;  // r-tile coordinates
+        const int y = ra0 + ra;
+        float fv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int x = rb0 + rb + s;
+            fv[s] = (ra < RA && rb + s < RB && y >= 0 && y < p.H && x >= 0 && x < p.W)
+                        ? p.f[(size_t)y * p.W + x] : 0.f;
+        }
+        if (ra < RA) {
+            float v[S];
+            // u-tile coordinates of r position (ra, rb): (ra - vl_min, rb - vc_min)
+            strip_sum<S, LMAX>(ut, upitch, ra - p.vl_min, rb - p.vc_min, cs, cw, p.n_cspans,
+                               cascade, v);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int x = rb0 + rb + s;
+                if (rb + s < RB && y >= 0 && y < p.H && x >= 0 && x < p.W)
+                    rt[ra * rpitch + rb + s] = rl_ratio(fv[s], v[s]);
+            }
+        }
+    }
+    __syncthreads();
+    // 2. out-of-image r positions take the value of their folded in-image position
+    for (int e = threadIdx.x; e < RA * RB; e += NW * 64) {
+        const int ra = e / RB, rb = e - ra * RB;
+        const int y = ra0 + ra, x = rb0 + rb;
+        if (y >= 0 && y < p.H && x >= 0 && x < p.W) continue;
+        const int fy = fold_idx(y, p.H, p.bc) - ra0, fx = fold_idx(x, p.W, p.bc) - rb0;
+        rt[ra * rpitch + rb] = rt[fy * rpitch + fx];
+    }
+    __syncthreads();
+    // 3. c = h^* * r on the output tile; u^{k+1} = u^k . c
+    float c[S];
+    // r-tile coordinates of output (lane, wv*S): (lane - cl_min, wv*S - cc_min)
+    strip_sum<S, LMAX>(rt, rpitch, lane - p.cl_min, wv * S - p.cc_min, rs, rw, p.n_rspans,
+                       cascade, c);
+    float un[S];
+    const int uy = lane - p.cl_min - p.vl_min;            // u-tile row of this output row
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int ux = wv * S + s - p.cc_min - p.vc_min;  // u-tile column
+        un[s] = __fmul_rn(ut[uy * upitch + ux], c[s]);
+    }
+    // coalesced store through LDS (the r tile is no longer needed)
+    constexpr int SP = TB + 1;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; ++s) rt[lane * SP + wv * S + s] = un[s];
+    __syncthreads();
+    for (int e = threadIdx.x; e < TA * TB; e += NW * 64) {
+        const int row = e / TB, col = e - row * TB;
+        u_out[(size_t)(a0 + row) * p.W + b0 + col] = rt[row * SP + col];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Resident line solver for axis-aligned box PSFs (1 x L or L x 1).  Such a PSF couples
 // pixels only along one image line, so every line is an independent 1-D RL problem.  A
 // workgroup keeps LINES whole lines of u and r in LDS (f in registers) and runs all
