@@ -86,12 +86,14 @@ typedef struct rl_thin {
                                (k - 1) % C == 0                                           */
 } rl_thin;
 
-/* Kernel-shape knobs (0 = let the library choose).  Results do not depend on them beyond
- * float32 rounding order.  strip: outputs per lane of the tiled kernels (8, 16 or 32);
- * seg: pixels per lane of the resident solver (2..32, power of two); lines_per_wg: image
- * lines per workgroup of the resident solver. */
+/* Kernel-shape and launch knobs (0 = let the library choose).  Results do not depend on
+ * them beyond float32 rounding order (graph_iters: not at all).  strip: outputs per lane of
+ * the tiled kernels (4, 8, 16 or 32); seg: pixels per lane of the resident solver (2..32,
+ * power of two); lines_per_wg: image lines per workgroup of the resident solver;
+ * graph_iters: plain two-pass jobs capture this many iterations into a hipGraph once and
+ * replay it from rl_iterate (0: launch kernels directly). */
 typedef struct rl_tuning {
-    int32_t strip, seg, lines_per_wg, reserved;
+    int32_t strip, seg, lines_per_wg, graph_iters;
 } rl_tuning;
 
 typedef struct rl_params {
@@ -223,6 +225,35 @@ rl_status rl_psf_runs(const float *psf, int32_t psf_h, int32_t psf_w, int32_t *r
 rl_status rl_timing_enable(int32_t on);
 rl_status rl_timing_read(const char *name, int64_t *launches, double *total_ms);
 rl_status rl_timing_reset(void);
+
+/*
+ * Autotuner.  rl_autotune times every candidate kernel shape for these parameters on the
+ * caller's data: strip length, two-pass or fused schedule and graph replay on/off for
+ * the tiled kernels; segment length and lines per workgroup for the resident solver.
+ * Each candidate runs n_iter untimed then n_iter timed iterations (HIP events on
+ * p->stream; the call synchronises that stream) with p->f as data and `ws` (device,
+ * >= rl_autotune_workspace_bytes(p) bytes, contents clobbered) as the job workspace.
+ * A schedule other than RL_SCHED_AUTO in p is kept; path, boundary, thinning and kahan
+ * are never changed.  The fastest pair (schedule, tuning) goes to *best_schedule / *best
+ * (either may be NULL except best) and its milliseconds per iteration to *best_ms, and is
+ * stored in the library's process-wide tuning cache under the key (path, PSF height and
+ * width, taps, runs, round(log2(height*width)), thinning on/off, requested schedule).
+ * From then on rl_workspace_bytes and rl_init with an all-zero p->tuning use the cached
+ * pair for every job with that key -- so compute workspace sizes after tuning, since
+ * rl_init rejects a workspace smaller than the configuration it picks.
+ * rl_tune_lookup copies the cached pair for p (RL_E_STATE if there is none).
+ * rl_tune_cache_save / _load write and merge the cache as text, one entry per line
+ * (RL_E_INVAL on an unreadable file or a malformed line; a failed load changes nothing).
+ * rl_tune_cache_clear empties it.  The cache is guarded by a mutex; tuning itself must
+ * not overlap other work on p->stream that the timing would include.
+ */
+rl_status rl_autotune_workspace_bytes(const rl_params *p, size_t *bytes);
+rl_status rl_autotune(const rl_params *p, void *ws, size_t ws_bytes, int32_t n_iter,
+                      int32_t *best_schedule, rl_tuning *best, double *best_ms);
+rl_status rl_tune_lookup(const rl_params *p, int32_t *schedule, rl_tuning *out);
+rl_status rl_tune_cache_save(const char *path);
+rl_status rl_tune_cache_load(const char *path);
+rl_status rl_tune_cache_clear(void);
 
 /* Describes the kernel configuration chosen for a job (for logs and tests):
  * path, schedule, tile height/width, strip length, spans, taps. */

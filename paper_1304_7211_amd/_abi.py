@@ -27,7 +27,9 @@ THINS = {"off": 0, "abs": 1, "rel": 2}
 EXPORTS = ["rl_status_str", "rl_workspace_bytes", "rl_init", "rl_iterate", "rl_result",
            "rl_destroy", "rl_batch_workspace_bytes", "rl_iterate_batch", "rl_get_state",
            "rl_set_state", "rl_active_list", "rl_thin_schedule", "rl_psf_runs",
-           "rl_timing_enable", "rl_timing_read", "rl_timing_reset", "rl_job_describe"]
+           "rl_timing_enable", "rl_timing_read", "rl_timing_reset", "rl_autotune_workspace_bytes",
+           "rl_autotune", "rl_tune_lookup", "rl_tune_cache_save", "rl_tune_cache_load",
+           "rl_tune_cache_clear", "rl_job_describe"]
 
 
 class rl_thin(ctypes.Structure):
@@ -38,7 +40,7 @@ class rl_thin(ctypes.Structure):
 
 class rl_tuning(ctypes.Structure):
     _fields_ = [("strip", ctypes.c_int32), ("seg", ctypes.c_int32),
-                ("lines_per_wg", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lines_per_wg", ctypes.c_int32), ("graph_iters", ctypes.c_int32)]
 
 
 class rl_params(ctypes.Structure):
@@ -100,6 +102,13 @@ def lib():
             "rl_timing_enable": (i32, [i32]),
             "rl_timing_read": (i32, [ctypes.c_char_p, P(i64), P(ctypes.c_double)]),
             "rl_timing_reset": (i32, []),
+            "rl_autotune_workspace_bytes": (i32, [P(rl_params), P(sz)]),
+            "rl_autotune": (i32, [P(rl_params), vp, sz, i32, P(i32), P(rl_tuning),
+                                  P(ctypes.c_double)]),
+            "rl_tune_lookup": (i32, [P(rl_params), P(i32), P(rl_tuning)]),
+            "rl_tune_cache_save": (i32, [ctypes.c_char_p]),
+            "rl_tune_cache_load": (i32, [ctypes.c_char_p]),
+            "rl_tune_cache_clear": (i32, []),
             "rl_job_describe": (i32, [vp, P(rl_job_info)]),
         }
         for name, (res, args) in sig.items():
@@ -227,6 +236,47 @@ def rl_timing_read(name):
 
 def rl_timing_reset():
     return check("rl_timing_reset", lib().rl_timing_reset())
+
+
+def rl_autotune_workspace_bytes(params):
+    n = ctypes.c_size_t(0)
+    check("rl_autotune_workspace_bytes",
+          lib().rl_autotune_workspace_bytes(ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def rl_autotune(params, ws_ptr, ws_bytes, n_iter):
+    """Returns (schedule, rl_tuning, milliseconds per iteration) of the fastest candidate."""
+    best = rl_tuning()
+    sched = ctypes.c_int32(0)
+    ms = ctypes.c_double(0)
+    check("rl_autotune", lib().rl_autotune(ctypes.byref(params), ws_ptr, ws_bytes, int(n_iter),
+                                           ctypes.byref(sched), ctypes.byref(best),
+                                           ctypes.byref(ms)))
+    return sched.value, best, ms.value
+
+
+def rl_tune_lookup(params):
+    """(schedule, rl_tuning) cached for these parameters, or None."""
+    out = rl_tuning()
+    sched = ctypes.c_int32(0)
+    s = lib().rl_tune_lookup(ctypes.byref(params), ctypes.byref(sched), ctypes.byref(out))
+    if s == RL_E_STATE:
+        return None
+    check("rl_tune_lookup", s)
+    return sched.value, out
+
+
+def rl_tune_cache_save(path):
+    return check("rl_tune_cache_save", lib().rl_tune_cache_save(str(path).encode()))
+
+
+def rl_tune_cache_load(path):
+    return check("rl_tune_cache_load", lib().rl_tune_cache_load(str(path).encode()))
+
+
+def rl_tune_cache_clear():
+    return check("rl_tune_cache_clear", lib().rl_tune_cache_clear())
 
 
 def rl_job_describe(job):

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <map>
+#include <fstream>
+#include <sstream>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -117,9 +119,60 @@ int next_pow2(int v) {
     return p;
 }
 
-// Decide path, schedule and kernel for a job.  Deterministic in (params, PSF).
+// ---- tuning cache ----------------------------------------------------------------------
+struct TuneKey {
+    int path, kh, kw, taps, runs, bucket, thin, schedule;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(path, kh, kw, taps, runs, bucket, thin, schedule) <
+               std::tie(o.path, o.kh, o.kw, o.taps, o.runs, o.bucket, o.thin, o.schedule);
+    }
+};
+struct TuneEntry {
+    int schedule;  // schedule to use when the job asks for RL_SCHED_AUTO
+    rl_tuning t;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+TuneKey tune_key(const rl_params* p, const rl::CompiledPsf& c) {
+    TuneKey k{};
+    k.path = p->path == RL_PATH_AUTO ? c.auto_path : p->path;
+    k.kh = c.kh;
+    k.kw = c.kw;
+    k.taps = c.n_taps;
+    k.runs = (int)c.runs.size();
+    double px = (double)p->height * p->width;
+    k.bucket = (int)std::lround(std::log2(std::max(1.0, px)));
+    k.thin = p->thin.mode != RL_THIN_OFF;
+    k.schedule = p->schedule;
+    return k;
+}
+
+bool tuning_is_default(const rl_tuning& t) {
+    return t.strip == 0 && t.seg == 0 && t.lines_per_wg == 0 && t.graph_iters == 0;
+}
+
+// Decide path, schedule and kernel for a job.  Deterministic in (params, PSF, cache).
+rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config* cfg,
+                            std::string* why);
+
 rl_status choose_config(const rl_params* p, const rl::CompiledPsf& c, Config* cfg,
                         std::string* why) {
+    if (tuning_is_default(p->tuning)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(p, c));
+        if (it != g_tune.end()) {
+            rl_params q = *p;
+            q.tuning = it->second.t;
+            if (q.schedule == RL_SCHED_AUTO) q.schedule = it->second.schedule;
+            return choose_config_raw(&q, c, cfg, why);
+        }
+    }
+    return choose_config_raw(p, c, cfg, why);
+}
+
+rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config* cfg,
+                            std::string* why) {
     const int H = p->height, W = p->width;
     const bool thin = p->thin.mode != RL_THIN_OFF;
     int path = p->path == RL_PATH_AUTO ? c.auto_path : p->path;
@@ -374,6 +427,9 @@ struct rl_job {
     PhaseArgs h_args[2];
     int32_t h_prefix[2];
     rlk::FusedArgs h_fargs;
+    hipGraphExec_t graph = nullptr;  // captured chunk of graph_iters plain iterations
+    int graph_n = 0;
+    int graph_par = 0;  // parity of k the captured chunk starts at (fused schedule)
     // the plane holding u^k: the fused schedule alternates between u and u2
     float* cur_u() const {
         return (cfg.kind == KIND_FUSED && (k & 1)) ? reinterpret_cast<float*>(ws + L.u2)
@@ -567,6 +623,49 @@ rl_status rebuild_lists(rl_job* j, hipStream_t s) {
     return RL_OK;
 }
 
+rl_status enqueue_iterations(rl_job* j, int32_t n);
+rl_status enqueue_direct(rl_job* j, int32_t n);
+
+// Capture n plain iterations of a tiled job into an executable graph (kernel nodes only),
+// on a private stream so the caller's stream is not put into capture mode.
+rl_status capture_graph(rl_job* j, int n) {
+    hipStream_t cs;
+    rl_status st = dev_err(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+    if (st) return st;
+    bool timing;
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        timing = g_timing;
+        g_timing = false;  // no event records inside the graph
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipStream_t keep = j->stream;
+        const int64_t k0 = j->k;
+        j->stream = cs;
+        st = enqueue_direct(j, n);
+        j->stream = keep;
+        j->k = k0;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (st == RL_OK) st = dev_err(e2, "end capture");
+    } else {
+        st = dev_err(e, "begin capture");
+    }
+    if (st == RL_OK) {
+        st = dev_err(hipGraphInstantiate(&j->graph, graph, nullptr, nullptr, 0), "instantiate");
+        if (st) j->graph = nullptr;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        g_timing = timing;
+    }
+    if (st == RL_OK) j->graph_n = n;
+    return st;
+}
+
 rl_status enqueue_iterations(rl_job* j, int32_t n) {
     const Config& c = j->cfg;
     hipStream_t s = j->stream;
@@ -597,6 +696,38 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
         j->k += n;
         return RL_OK;
     }
+    const bool thin = j->p.thin.mode != RL_THIN_OFF;
+    const int gi = j->p.tuning.graph_iters;
+    if (!thin && gi > 0 && n >= gi) {
+        // Plain jobs: the launch sequence of the two-pass schedule does not depend on k,
+        // and the fused kernel only uses the parity of k (which plane holds u^k), so one
+        // captured chunk can be replayed at any k of the captured parity; fused chunks
+        // have an even length, which keeps that parity.
+        if (!j->graph) {
+            const int gn = c.kind == KIND_FUSED ? (gi + 1) & ~1 : gi;
+            rl_status st = capture_graph(j, gn);
+            if (st) return st;
+            j->graph_par = (int)(j->k & 1);
+        }
+        if (c.kind == KIND_FUSED && (int)(j->k & 1) != j->graph_par) {
+            rl_status st = enqueue_direct(j, 1);
+            if (st) return st;
+            --n;
+        }
+        while (j->graph && j->graph_n > 0 && n >= j->graph_n) {
+            rl_status st = dev_err(hipGraphLaunch(j->graph, s), "graph launch");
+            if (st) return st;
+            j->k += j->graph_n;
+            n -= j->graph_n;
+        }
+    }
+    return enqueue_direct(j, n);
+}
+
+// Launch n iterations of a tiled or fused job one kernel at a time.
+rl_status enqueue_direct(rl_job* j, int32_t n) {
+    const Config& c = j->cfg;
+    hipStream_t s = j->stream;
     if (c.kind == KIND_FUSED) {
         const rlk::FusedArgs* table = j->at<rlk::FusedArgs>(j->L.fargs);
         for (int i = 0; i < n; ++i) {
@@ -618,6 +749,8 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
     lb.table = la.table + 1;
     la.prefix = lb.prefix = j->at<int32_t>(j->L.prefix);
     la.n_jobs = lb.n_jobs = 1;
+    la.one = j->h_args[0];
+    lb.one = j->h_args[1];
     for (int i = 0; i < n; ++i) {
         if (thin && !is_full(j->k, j->p.thin.reset_period) &&
             (!j->list_valid ||
@@ -870,6 +1003,7 @@ rl_status rl_destroy(rl_job* j) {
     if (!j) return RL_E_INVAL;
     if (!j->live) return RL_E_STATE;
     j->live = false;
+    if (j->graph) (void)hipGraphExecDestroy(j->graph);
     delete j;
     return RL_OK;
 }
@@ -1011,6 +1145,10 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
                 la.prefix = reinterpret_cast<const int32_t*>(base + g.off_p);
                 la.n_jobs = m;
                 la.kb = kb;
+                if (m == 1) {
+                    rl_job* j1 = jobs[g.idx[0]];
+                    la.one = phase_args(j1, phase == 1, j1->k);
+                }
                 st = dev_err(launch(phase ? g.nb : g.na, phase ? g.fb : g.fa, dim3(g.prefix[m]),
                                     dim3(kNW * 64), phase ? g.lds_b : g.lds_a, gsm, la),
                              phase ? g.nb : g.na);
@@ -1158,6 +1296,182 @@ rl_status rl_timing_reset(void) {
         (void)hipEventDestroy(t.b);
     }
     g_timed.clear();
+    return RL_OK;
+}
+
+namespace {
+
+// Candidate (schedule, tuning) pairs for a job's kernel family.
+std::vector<TuneEntry> tune_candidates(const rl_params* p, const Config& base) {
+    std::vector<TuneEntry> v;
+    auto add = [&](int sched, int strip, int seg, int lpw, int gi) {
+        TuneEntry e{};
+        e.schedule = p->schedule == RL_SCHED_AUTO ? sched : p->schedule;
+        e.t.strip = strip;
+        e.t.seg = seg;
+        e.t.lines_per_wg = lpw;
+        e.t.graph_iters = gi;
+        v.push_back(e);
+    };
+    const bool thin = p->thin.mode != RL_THIN_OFF;
+    if (base.kind == KIND_RESIDENT) {
+        for (int seg : {4, 8, 16})
+            for (int lpw : {1, 2, 4}) add(RL_SCHED_RESIDENT, 0, seg, lpw, 0);
+        return v;
+    }
+    const int gi = thin ? 0 : 16;
+    for (int strip : {4, 8, 16}) {
+        add(RL_SCHED_TWO_PASS, strip, 0, 0, 0);
+        if (gi) add(RL_SCHED_TWO_PASS, strip, 0, 0, gi);
+    }
+    if (base.kind == KIND_SLIDE) add(RL_SCHED_TWO_PASS, 32, 0, 0, gi);
+    if (!thin && p->schedule == RL_SCHED_AUTO) {
+        add(RL_SCHED_FUSED, 0, 0, 0, 0);
+        add(RL_SCHED_FUSED, 0, 0, 0, gi);
+    }
+    return v;
+}
+
+rl_params with_entry(const rl_params* p, const TuneEntry& e) {
+    rl_params q = *p;
+    q.tuning = e.t;
+    q.schedule = e.schedule;
+    return q;
+}
+
+}  // namespace
+
+rl_status rl_autotune_workspace_bytes(const rl_params* p, size_t* bytes) {
+    std::string why;
+    if (!bytes) return RL_E_INVAL;
+    rl_status st = validate_params(p, &why);
+    if (st) return st;
+    rl::CompiledPsf c;
+    if (!rl::compile_psf(p->psf, p->psf_h, p->psf_w, &c, &why)) return RL_E_INVAL;
+    Config base;
+    if ((st = choose_config_raw(p, c, &base, &why))) return st;
+    size_t mx = make_layout(p, base).total;
+    for (const TuneEntry& e : tune_candidates(p, base)) {
+        rl_params q = with_entry(p, e);
+        Config cfg;
+        if (choose_config_raw(&q, c, &cfg, &why) != RL_OK) continue;
+        mx = std::max(mx, make_layout(&q, cfg).total);
+    }
+    *bytes = mx;
+    return RL_OK;
+}
+
+rl_status rl_autotune(const rl_params* p, void* ws, size_t ws_bytes, int32_t n_iter,
+                      int32_t* best_schedule, rl_tuning* best, double* best_ms) {
+    std::string why;
+    if (!best || n_iter < 1) return RL_E_INVAL;
+    rl_status st = validate_params(p, &why);
+    if (st) return st;
+    rl::CompiledPsf c;
+    if (!rl::compile_psf(p->psf, p->psf_h, p->psf_w, &c, &why)) return RL_E_INVAL;
+    Config base;
+    if ((st = choose_config_raw(p, c, &base, &why))) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(p->stream);
+    hipEvent_t a, b;
+    if ((st = dev_err(hipEventCreate(&a), "event"))) return st;
+    if ((st = dev_err(hipEventCreate(&b), "event"))) { (void)hipEventDestroy(a); return st; }
+    double bt = 1e300;
+    TuneEntry bestt{};
+    bool found = false;
+    for (const TuneEntry& e : tune_candidates(p, base)) {
+        rl_params q = with_entry(p, e);
+        Config cfg;
+        if (choose_config_raw(&q, c, &cfg, &why) != RL_OK) continue;  // not applicable
+        rl_job* j = nullptr;
+        if (rl_init(&q, ws, ws_bytes, &j) != RL_OK) continue;
+        // the warm-up covers one full timed chunk, so graph capture is not timed
+        st = rl_iterate(j, n_iter);
+        if (st == RL_OK) st = dev_err(hipEventRecord(a, s), "event");
+        if (st == RL_OK) st = rl_iterate(j, n_iter);
+        if (st == RL_OK) st = dev_err(hipEventRecord(b, s), "event");
+        if (st == RL_OK) st = dev_err(hipEventSynchronize(b), "event");
+        float ms = 0;
+        if (st == RL_OK) st = dev_err(hipEventElapsedTime(&ms, a, b), "event");
+        rl_destroy(j);
+        if (st) break;
+        const double per = ms / n_iter;
+        if (per < bt) {
+            bt = per;
+            bestt = e;
+            found = true;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st) return st;
+    if (!found) return RL_E_UNSUPPORTED;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(p, c)] = bestt;
+    }
+    *best = bestt.t;
+    if (best_schedule) *best_schedule = bestt.schedule;
+    if (best_ms) *best_ms = bt;
+    return RL_OK;
+}
+
+rl_status rl_tune_lookup(const rl_params* p, int32_t* schedule, rl_tuning* out) {
+    std::string why;
+    if (!p || !out) return RL_E_INVAL;
+    rl::CompiledPsf c;
+    if (!rl::compile_psf(p->psf, p->psf_h, p->psf_w, &c, &why)) return RL_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(p, c));
+    if (it == g_tune.end()) return RL_E_STATE;
+    *out = it->second.t;
+    if (schedule) *schedule = it->second.schedule;
+    return RL_OK;
+}
+
+rl_status rl_tune_cache_save(const char* path) {
+    if (!path) return RL_E_INVAL;
+    std::ofstream o(path);
+    if (!o) return RL_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    o << "# rl tuning cache: path kh kw taps runs bucket thin schedule -> "
+         "schedule strip seg lines_per_wg graph_iters\n";
+    for (const auto& kv : g_tune) {
+        const TuneKey& k = kv.first;
+        const rl_tuning& t = kv.second.t;
+        o << k.path << ' ' << k.kh << ' ' << k.kw << ' ' << k.taps << ' ' << k.runs << ' '
+          << k.bucket << ' ' << k.thin << ' ' << k.schedule << ' ' << kv.second.schedule << ' '
+          << t.strip << ' ' << t.seg << ' ' << t.lines_per_wg << ' ' << t.graph_iters << '\n';
+    }
+    return o ? RL_OK : RL_E_INVAL;
+}
+
+rl_status rl_tune_cache_load(const char* path) {
+    if (!path) return RL_E_INVAL;
+    std::ifstream in(path);
+    if (!in) return RL_E_INVAL;
+    std::map<TuneKey, TuneEntry> loaded;
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ss(line);
+        TuneKey k{};
+        TuneEntry e{};
+        if (!(ss >> k.path >> k.kh >> k.kw >> k.taps >> k.runs >> k.bucket >> k.thin >> k.schedule >>
+              e.schedule >> e.t.strip >> e.t.seg >> e.t.lines_per_wg >> e.t.graph_iters))
+            return RL_E_INVAL;
+        if (e.schedule < RL_SCHED_AUTO || e.schedule > RL_SCHED_FUSED || e.t.strip < 0 ||
+            e.t.seg < 0 || e.t.lines_per_wg < 0 || e.t.graph_iters < 0)
+            return RL_E_INVAL;
+        loaded[k] = e;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : loaded) g_tune[kv.first] = kv.second;
+    return RL_OK;
+}
+
+rl_status rl_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
     return RL_OK;
 }
 

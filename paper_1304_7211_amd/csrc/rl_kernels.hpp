@@ -117,8 +117,9 @@ struct PhaseArgs {
 struct LaunchArgs {
     const PhaseArgs* table;
     const int32_t* prefix;
-    int32_t n_jobs, pad;
+    int32_t n_jobs, n_tiles1;  // n_tiles1: tile count when n_jobs == 1
     int64_t kb;
+    PhaseArgs one;             // the job itself when n_jobs == 1 (saves a dependent load)
 };
 
 typedef const __attribute__((address_space(4))) PhaseArgs* ConstArgsPtr;
@@ -183,17 +184,22 @@ __device__ __forceinline__ void thin_finalize_wave(int32_t* act_part, int64_t* s
 template <bool PHASE_B>
 __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int TA, int TB,
                                         int& a0, int& b0) {
-    const ConstIntPtr pre = (ConstIntPtr)L.prefix;
-    int lo = 0, hi = L.n_jobs - 1;
     const int b = blockIdx.x;
-    while (lo < hi) {  // last job with prefix <= b
-        int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= b) lo = mid;
-        else hi = mid - 1;
+    int local;
+    if (L.n_jobs == 1) {
+        p = L.one;
+        local = b;
+    } else {
+        const ConstIntPtr pre = (ConstIntPtr)L.prefix;
+        int lo = 0, hi = L.n_jobs - 1;
+        while (lo < hi) {  // last job with prefix <= b
+            int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        p = load_args((ConstArgsPtr)L.table + lo);
+        local = b - pre[lo];
     }
-    p = load_args((ConstArgsPtr)L.table + lo);
-    const int local = b - pre[lo];
-    const int nb_job = pre[lo + 1] - pre[lo];
     p.k += L.kb;
     bool use_list = false;
     if (p.cnt) {

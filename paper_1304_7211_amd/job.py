@@ -42,12 +42,34 @@ def make_params(f, psf, boundary="reflect", path="auto", schedule="auto", kahan=
         p.tuning.strip = int(tuning.get("strip", 0))
         p.tuning.seg = int(tuning.get("seg", 0))
         p.tuning.lines_per_wg = int(tuning.get("lines_per_wg", 0))
+        p.tuning.graph_iters = int(tuning.get("graph_iters", 0))
     return p, psf  # keep psf alive until rl_init has copied it
 
 
 def workspace_bytes(f, psf, **kw):
     p, _keep = make_params(f, psf, **kw)
     return A.rl_workspace_bytes(p)
+
+
+def tuning_dict(t):
+    return dict(strip=t.strip, seg=t.seg, lines_per_wg=t.lines_per_wg, graph_iters=t.graph_iters)
+
+
+def autotune(f, psf, n_iter=10, **kw):
+    """Time the candidate kernel shapes on (f, psf) and cache the fastest for jobs of the
+    same kind.  Returns dict(schedule=..., tuning=..., ms_per_iter=...)."""
+    p, keep = make_params(f, psf, **kw)
+    ws = torch.empty(A.rl_autotune_workspace_bytes(p), dtype=torch.uint8, device=f.device)
+    sched, t, ms = A.rl_autotune(p, ws.data_ptr(), ws.numel(), n_iter)
+    del keep
+    return dict(schedule=A.SCHED_NAMES[sched], tuning=tuning_dict(t), ms_per_iter=ms)
+
+
+def tune_lookup(f, psf, **kw):
+    p, keep = make_params(f, psf, **kw)
+    r = A.rl_tune_lookup(p)
+    del keep
+    return None if r is None else dict(schedule=A.SCHED_NAMES[r[0]], tuning=tuning_dict(r[1]))
 
 
 class Job:

@@ -142,3 +142,55 @@ def test_null_and_state_errors(A):
     n = ctypes.c_int32(0)
     assert L.rl_psf_runs(np.zeros((2, 2), np.float32).ctypes.data, 2, 2, None, None, 0,
                          ctypes.byref(n), None) == A.RL_E_INVAL
+
+
+def test_tune_cache_roundtrip(A, tmp_path):
+    """The tuning cache (host side only): load, lookup, effect on the workspace size,
+    save/reload, rejection of malformed files, clear."""
+    A.rl_tune_cache_clear()
+    psf = synth.disc(5)
+    p, keep = _params(A, H=512, W=512, psf=psf)
+    assert A.rl_tune_lookup(p) is None
+    base = A.rl_workspace_bytes(p)
+    runs = len(oracle.psf_runs(psf)[0])
+    taps = int(np.count_nonzero(psf))
+    bucket = 18  # round(log2(512 * 512))
+    # key: path kh kw taps runs bucket thin schedule -> schedule strip seg lpw graph_iters
+    f1 = tmp_path / "a.txt"
+    f1.write_text("# comment\n"
+                  f"3 11 11 {taps} {runs} {bucket} 0 0 1 16 0 0 8\n")
+    A.rl_tune_cache_load(f1)
+    got = A.rl_tune_lookup(p)
+    assert got is not None
+    sched, t = got
+    assert (sched, t.strip, t.seg, t.lines_per_wg, t.graph_iters) == (1, 16, 0, 0, 8)
+    # a neighbouring size bucket and a thinned job do not match the entry
+    q, k2 = _params(A, H=64, W=64, psf=psf)
+    assert A.rl_tune_lookup(q) is None
+    q2, k3 = _params(A, H=512, W=512, psf=psf, thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
+    assert A.rl_tune_lookup(q2) is None
+    # the cached strip length reaches the configuration (and so the workspace layout)
+    p.tuning.strip = 16
+    explicit = A.rl_workspace_bytes(p)
+    p.tuning.strip = 0
+    assert A.rl_workspace_bytes(p) == explicit
+    # save, clear, reload
+    f2 = tmp_path / "b.txt"
+    A.rl_tune_cache_save(f2)
+    A.rl_tune_cache_clear()
+    assert A.rl_tune_lookup(p) is None
+    assert A.rl_workspace_bytes(p) == base
+    A.rl_tune_cache_load(f2)
+    assert A.rl_tune_lookup(p)[1].strip == 16
+    # malformed lines are rejected and leave the cache as it was
+    for bad in ["3 11 11\n", f"3 11 11 {taps} {runs} {bucket} 0 0 9 16 0 0 8\n",
+                f"3 11 11 {taps} {runs} {bucket} 0 0 1 -4 0 0 8\n"]:
+        f3 = tmp_path / "bad.txt"
+        f3.write_text(bad)
+        with pytest.raises(A.RLError):
+            A.rl_tune_cache_load(f3)
+    assert A.rl_tune_lookup(p)[1].strip == 16
+    with pytest.raises(A.RLError):
+        A.rl_tune_cache_load(tmp_path / "missing.txt")
+    A.rl_tune_cache_clear()
+    assert A.rl_tune_lookup(p) is None
