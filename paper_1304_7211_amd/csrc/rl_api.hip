@@ -31,7 +31,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kNW = 4;  // wavefronts per workgroup in the tiled kernels
+constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
@@ -263,10 +263,11 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     const int64_t npx = (int64_t)H * W;
     // outputs per lane: long strips amortise seeds and windows, short strips give the
     // latency-bound kernels more wavefronts on small images
-    // defaults from measurements on 1024^2 and 2048^2 images (span: 8 outputs per lane;
-    // sliding runs: 8 below 4 Mpx, 16 from there on)
-    const int span_S = p->tuning.strip ? p->tuning.strip : 8;
-    const int slide_S = p->tuning.strip ? p->tuning.strip : (npx >= (int64_t)4 << 20 ? 16 : 8);
+    // defaults from measurements with 8 wavefronts per workgroup on 64^2 .. 2048^2 images:
+    // 4 outputs per lane below 0.5 Mpx, 8 from there on
+    const int def_S = npx >= ((int64_t)1 << 19) ? 8 : 4;
+    const int span_S = p->tuning.strip ? p->tuning.strip : def_S;
+    const int slide_S = p->tuning.strip ? p->tuning.strip : def_S;
     if (span_S != 4 && span_S != 8 && span_S != 16 && span_S != 32) { *why = "tuning.strip"; return RL_E_INVAL; }
     if (path == RL_PATH_DIRECT) {
         cfg->kind = KIND_SPAN;

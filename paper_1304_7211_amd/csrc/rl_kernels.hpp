@@ -54,6 +54,14 @@ __device__ __forceinline__ DevSpan load_span(ConstSpanPtr t, int i) {
     return s;
 }
 
+// Index of this wavefront within its workgroup.  threadIdx.x >> 6 is the same for every
+// lane of a wavefront, but the compiler cannot prove it; reading it through readfirstlane
+// makes it a scalar, so loops and branches on it run on the scalar unit without exec-mask
+// bookkeeping.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 // Boundary fold of index i into [0, n) (Section 2, "Boundary treatment").
 __device__ __forceinline__ int fold_idx(int i, int n, int bc) {
     if ((unsigned)i < (unsigned)n) return i;
@@ -228,7 +236,9 @@ __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int T
 // (coalesced), and every (row, 64-column chunk) is one global-to-LDS DMA load
 // (global_load_lds_dword: no VGPRs, no dependence on earlier loads), so the whole tile is
 // in flight at once.  Lanes past the row end are masked off, so the DMA never writes
-// outside the row.  The caller waits (lds_dma_wait) and synchronises before reading.
+// outside the row.  Column folds and lane masks are computed once; the row loop runs on
+// the scalar unit (row, its fold and the LDS row address are wavefront-uniform).  The
+// caller waits (lds_dma_wait) and synchronises before reading.
 constexpr int MAXC = 5;
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -236,12 +246,14 @@ __device__ __forceinline__ void load_tile(float* lds, const float* __restrict__ 
                                           int W, int bc, int ly0, int lx0, int ny, int nx,
                                           int pitch) {
     const int nwv = blockDim.x >> 6;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     int gx[MAXC];
+    bool on[MAXC];
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) {
-        int col = lane + 64 * c;
-        gx[c] = col < nx ? fold_idx(lx0 + col, W, bc) : 0;
+        const int col = lane + 64 * c;
+        on[c] = col < nx;
+        gx[c] = on[c] ? fold_idx(lx0 + col, W, bc) : 0;
     }
     const int nch = (nx + 63) >> 6;
     for (int row = wv; row < ny; row += nwv) {
@@ -249,11 +261,9 @@ __device__ __forceinline__ void load_tile(float* lds, const float* __restrict__ 
         float* drow = lds + row * pitch;
 #pragma unroll
         for (int c = 0; c < MAXC; ++c) {
-            if (c < nch) {
-                if (lane + 64 * c < nx)
-                    __builtin_amdgcn_global_load_lds((const void*)(srow + gx[c]),
-                                                     (lds_void*)(drow + 64 * c), 4, 0, 0);
-            }
+            if (c < nch && on[c])
+                __builtin_amdgcn_global_load_lds((const void*)(srow + gx[c]),
+                                                 (lds_void*)(drow + 64 * c), 4, 0, 0);
         }
     }
 }
@@ -304,7 +314,7 @@ __device__ __forceinline__ void add_active(const PhaseArgs& p, int n_active) {
     if (!p.cnt) return;
     for (int off = 32; off > 0; off >>= 1) n_active += __shfl_xor(n_active, off);
     if ((threadIdx.x & 63) == 0 && n_active) {
-        const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % ACT_SLOTS);
+        const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave_id()) % ACT_SLOTS);
         atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + slot], n_active);
     }
 }
@@ -357,7 +367,7 @@ struct EpiPlan {
 template <int ORIENT, int S, int NW>
 __device__ __forceinline__ void epi_pos(int i, int a0, int b0, int& y, int& x) {
     constexpr int TB = NW * S;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     if (ORIENT == ORIENT_COLS) {
         x = a0 + lane;
         y = b0 + wv * S + i;
@@ -384,7 +394,7 @@ template <int ORIENT, int S, int NW, bool PHASE_B>
 __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, int a0, int b0,
                                               const float (&out)[S],
                                               const EpiPlan<ORIENT, S, NW>& plan) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     int n_active = 0;
     if (ORIENT == ORIENT_COLS) {
 #pragma unroll
@@ -457,7 +467,7 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     lds_dma_wait();
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int la = lane - p.lane_min;
     const int lb = wv * S - p.c_min;
     float acc0[S], acc1[S], part[S];
@@ -526,47 +536,67 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
     lds_dma_wait();
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int la = lane - p.lane_min;
     const int lb = wv * S - p.c_min;   // this wavefront's strip start
     const int lb0 = -p.c_min;          // the tile's first output
     const bool kahan = p.kahan != 0;
+    const ConstSpanPtr spans = as_const(p.spans);
+    // this wavefront's share of the seed: spans i with i % NW == wv, in increasing i
     float seed = 0.f, seed_c = 0.f;
+    for (int i = wv; i < p.n_spans; i += NW) {
+        const DevSpan sp = load_span(spans, i);
+        const int ia = la + sp.lane_off, ib0 = lb0 + sp.c0;
+        const int len = sp.len;
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+        int q = 0;
+        for (; q + 4 <= len; q += 4) {
+            p0 += lds[g.idx(ia, ib0 + q)];
+            p1 += lds[g.idx(ia, ib0 + q + 1)];
+            p2 += lds[g.idx(ia, ib0 + q + 2)];
+            p3 += lds[g.idx(ia, ib0 + q + 3)];
+        }
+        for (; q < len; ++q) p0 += lds[g.idx(ia, ib0 + q)];
+        const float part = (p0 + p1) + (p2 + p3);
+        if (kahan) kahan_add(seed, seed_c, sp.w0 * part);
+        else seed = fmaf(sp.w0, part, seed);
+    }
+    // per-step changes d[s] (step into output s of the strip), accumulated over the spans
+    // in increasing order; U spans per loop trip so that their descriptor and LDS reads are
+    // in flight together.  d[0] of the first wavefront stays 0 (its first output is the seed).
+    constexpr int U = S <= 8 ? 2 : 1;
     float d[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) d[s] = 0.f;
-    const ConstSpanPtr spans = as_const(p.spans);
-    for (int i = 0; i < p.n_spans; ++i) {
-        const DevSpan sp = load_span(spans, i);
-        const float w = sp.w0;
-        const int ia = la + sp.lane_off, ib = lb + sp.c0;
-        const int len = sp.len;
-        if (i % NW == wv) {  // this wavefront's share of the seed
-            const int ib0 = lb0 + sp.c0;
-            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-            int q = 0;
-            for (; q + 4 <= len; q += 4) {
-                p0 += lds[g.idx(ia, ib0 + q)];
-                p1 += lds[g.idx(ia, ib0 + q + 1)];
-                p2 += lds[g.idx(ia, ib0 + q + 2)];
-                p3 += lds[g.idx(ia, ib0 + q + 3)];
+    const int s_first = wv > 0 ? 0 : 1;
+    int i = 0;
+    for (; i + U <= p.n_spans; i += U) {
+        float w[U], din[U][S], dout[U][S];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const DevSpan sp = load_span(spans, i + u);
+            w[u] = sp.w0;
+            const int ia = la + sp.lane_off, ib = lb + sp.c0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                din[u][s] = lds[g.idx(ia, ib + s + sp.len - 1)];
+                dout[u][s] = lds[g.idx(ia, ib + s - 1)];
             }
-            for (; q < len; ++q) p0 += lds[g.idx(ia, ib0 + q)];
-            const float part = (p0 + p1) + (p2 + p3);
-            if (kahan) kahan_add(seed, seed_c, w * part);
-            else seed = fmaf(w, part, seed);
-        }
-        if (wv > 0) {
-            const float in = lds[g.idx(ia, ib + len - 1)];
-            const float outv = lds[g.idx(ia, ib - 1)];
-            d[0] = fmaf(w, in - outv, d[0]);
         }
 #pragma unroll
-        for (int s = 1; s < S; ++s) {
-            const float in = lds[g.idx(ia, ib + s + len - 1)];
-            const float outv = lds[g.idx(ia, ib + s - 1)];
-            d[s] = fmaf(w, in - outv, d[s]);
-        }
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (s >= s_first) d[s] = fmaf(w[u], din[u][s] - dout[u][s], d[s]);
+    }
+    for (; i < p.n_spans; ++i) {
+        const DevSpan sp = load_span(spans, i);
+        const int ia = la + sp.lane_off, ib = lb + sp.c0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (s >= s_first)
+                d[s] = fmaf(sp.w0, lds[g.idx(ia, ib + s + sp.len - 1)] - lds[g.idx(ia, ib + s - 1)],
+                            d[s]);
     }
     // prefix of the changes inside the strip (value P, compensation C: true sum = P - C)
     float P[S], C[S];
@@ -717,7 +747,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(const FusedArgs* table, 
     lds_dma_wait();
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const bool cascade = p.kahan != 0;
     const ConstSpanPtr cs = as_const(p.cspans), rs = as_const(p.rspans);
     const ConstFloatPtr cw = as_const(p.cwts), rw = as_const(p.rwts);
@@ -1008,7 +1038,7 @@ __global__ __launch_bounds__(256) void thin_scatter_kernel(ThinListArgs a) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool act = (p < a.N) && ((int)a.cnt[p] < a.hyst);
     unsigned long long m = __ballot(act);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     if (lane == 0) wsum[wv] = __popcll(m);
     __syncthreads();
     int base = a.block_offsets[blockIdx.x];
@@ -1024,7 +1054,7 @@ __global__ __launch_bounds__(1024) void tile_compact_kernel(int32_t* tflag, int 
     __shared__ int base_s;
     if (threadIdx.x == 0) base_s = 0;
     __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     for (int t0 = 0; t0 < n; t0 += 1024) {
         int t = t0 + threadIdx.x;
         bool on = t < n && tflag[t] != 0;
