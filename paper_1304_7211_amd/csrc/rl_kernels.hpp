@@ -41,15 +41,20 @@ typedef const __attribute__((address_space(4))) DevSpan* ConstSpanPtr;
 typedef const __attribute__((address_space(4))) float* ConstFloatPtr;
 __device__ __forceinline__ ConstSpanPtr as_const(const DevSpan* p) { return (ConstSpanPtr)p; }
 __device__ __forceinline__ ConstFloatPtr as_const(const float* p) { return (ConstFloatPtr)p; }
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) i32x4* ConstI32x4Ptr;
+// One span descriptor as two 16-byte scalar loads (the compiler merges them into one).
 __device__ __forceinline__ DevSpan load_span(ConstSpanPtr t, int i) {
+    const ConstI32x4Ptr q = (ConstI32x4Ptr)(t + i);
+    const i32x4 a = q[0], b = q[1];
     DevSpan s;
-    s.lane_off = t[i].lane_off;
-    s.c0 = t[i].c0;
-    s.len = t[i].len;
-    s.woff = t[i].woff;
-    s.w0 = t[i].w0;
-    s.uniform = t[i].uniform;
-    s.row_end = t[i].row_end;
+    s.lane_off = a.x;
+    s.c0 = a.y;
+    s.len = a.z;
+    s.woff = a.w;
+    s.w0 = __int_as_float(b.x);
+    s.uniform = b.y;
+    s.row_end = b.z;
     s.pad = 0;
     return s;
 }
@@ -328,6 +333,16 @@ struct TileGeom {
     __device__ __forceinline__ int idx(int a, int b) const {
         return ORIENT == ORIENT_ROWS ? a * pitch + b : b * pitch + a;
     }
+    // idx(la + da, b) split into a per-lane part (computed once per kernel) and a
+    // wavefront-uniform part (scalar arithmetic per span).
+    __device__ __forceinline__ int lane_part(int la) const {
+        return ORIENT == ORIENT_ROWS ? la * pitch : la;
+    }
+    __device__ __forceinline__ int uni_part(int da, int b) const {
+        return ORIENT == ORIENT_ROWS ? da * pitch + b : b * pitch + da;
+    }
+    // distance between neighbouring strip positions
+    __device__ __forceinline__ int bstep() const { return ORIENT == ORIENT_ROWS ? 1 : pitch; }
 };
 
 template <int ORIENT>
@@ -436,14 +451,15 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
 // table is the DIRECT path.
 // ---------------------------------------------------------------------------------------
 template <int ORIENT, int S, int L>
-__device__ __forceinline__ void span_piece(const float* lds, const TileGeom<ORIENT>& g, int ia,
-                                           int ib, ConstFloatPtr wp, float (&part)[S]) {
+__device__ __forceinline__ void span_piece(const float* base, const TileGeom<ORIENT>& g,
+                                           ConstFloatPtr wp, float (&part)[S]) {
     float w[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) w[t] = wp[t];
     float win[S + L - 1];
+    const int st = g.bstep();
 #pragma unroll
-    for (int q = 0; q < S + L - 1; ++q) win[q] = lds[g.idx(ia, ib + q)];
+    for (int q = 0; q < S + L - 1; ++q) win[q] = base[q * st];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         float a = part[s];
@@ -468,7 +484,7 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wv = wave_id();
-    const int la = lane - p.lane_min;
+    const float* lane_lds = lds + g.lane_part(lane - p.lane_min);
     const int lb = wv * S - p.c_min;
     float acc0[S], acc1[S], part[S];
 #pragma unroll
@@ -481,11 +497,11 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     for (int i = 0; i < p.n_spans; ++i) {
         const DevSpan sp = load_span(spans, i);
         const ConstFloatPtr wp = wts + sp.woff;
-        const int ia = la + sp.lane_off, ib = lb + sp.c0;
+        const float* base = lane_lds + g.uni_part(sp.lane_off, lb + sp.c0);
         switch (sp.len) {
 #define RL_PIECE(n) \
     case n:         \
-        if (n <= LMAX) span_piece<ORIENT, S, (n <= LMAX ? n : 1)>(lds, g, ia, ib, wp, part); \
+        if (n <= LMAX) span_piece<ORIENT, S, (n <= LMAX ? n : 1)>(base, g, wp, part); \
         break;
             RL_PIECE(1) RL_PIECE(2) RL_PIECE(3) RL_PIECE(4) RL_PIECE(5) RL_PIECE(6)
             RL_PIECE(7) RL_PIECE(8) RL_PIECE(9) RL_PIECE(10) RL_PIECE(11) RL_PIECE(12)
@@ -537,67 +553,70 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wv = wave_id();
-    const int la = lane - p.lane_min;
+    const float* lane_lds = lds + g.lane_part(lane - p.lane_min);
     const int lb = wv * S - p.c_min;   // this wavefront's strip start
     const int lb0 = -p.c_min;          // the tile's first output
+    const int st = g.bstep();
     const bool kahan = p.kahan != 0;
     const ConstSpanPtr spans = as_const(p.spans);
     // this wavefront's share of the seed: spans i with i % NW == wv, in increasing i
     float seed = 0.f, seed_c = 0.f;
     for (int i = wv; i < p.n_spans; i += NW) {
         const DevSpan sp = load_span(spans, i);
-        const int ia = la + sp.lane_off, ib0 = lb0 + sp.c0;
+        const float* base = lane_lds + g.uni_part(sp.lane_off, lb0 + sp.c0);
         const int len = sp.len;
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         int q = 0;
         for (; q + 4 <= len; q += 4) {
-            p0 += lds[g.idx(ia, ib0 + q)];
-            p1 += lds[g.idx(ia, ib0 + q + 1)];
-            p2 += lds[g.idx(ia, ib0 + q + 2)];
-            p3 += lds[g.idx(ia, ib0 + q + 3)];
+            p0 += base[q * st];
+            p1 += base[(q + 1) * st];
+            p2 += base[(q + 2) * st];
+            p3 += base[(q + 3) * st];
         }
-        for (; q < len; ++q) p0 += lds[g.idx(ia, ib0 + q)];
+        for (; q < len; ++q) p0 += base[q * st];
         const float part = (p0 + p1) + (p2 + p3);
         if (kahan) kahan_add(seed, seed_c, sp.w0 * part);
         else seed = fmaf(sp.w0, part, seed);
     }
     // per-step changes d[s] (step into output s of the strip), accumulated over the spans
     // in increasing order; U spans per loop trip so that their descriptor and LDS reads are
-    // in flight together.  d[0] of the first wavefront stays 0 (its first output is the seed).
+    // in flight together.  The first wavefront's d[0] is not a step (its first output is
+    // the seed): it reads an in-tile neighbour instead and is cleared afterwards.
     constexpr int U = S <= 8 ? 2 : 1;
     float d[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) d[s] = 0.f;
-    const int s_first = wv > 0 ? 0 : 1;
+    const int z0 = wv == 0 ? 1 : 0;
     int i = 0;
     for (; i + U <= p.n_spans; i += U) {
-        float w[U], din[U][S], dout[U][S];
+        DevSpan sp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) sp[u] = load_span(spans, i + u);
+        float din[U][S], dout[U][S];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const DevSpan sp = load_span(spans, i + u);
-            w[u] = sp.w0;
-            const int ia = la + sp.lane_off, ib = lb + sp.c0;
+            const float* base = lane_lds + g.uni_part(sp[u].lane_off, lb + sp[u].c0);
+            const float* bin = base + (sp[u].len - 1) * st;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                din[u][s] = lds[g.idx(ia, ib + s + sp.len - 1)];
-                dout[u][s] = lds[g.idx(ia, ib + s - 1)];
+                din[u][s] = bin[s * st];
+                dout[u][s] = base[(s == 0 ? z0 - 1 : s - 1) * st];
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (s >= s_first) d[s] = fmaf(w[u], din[u][s] - dout[u][s], d[s]);
+            for (int s = 0; s < S; ++s) d[s] = fmaf(sp[u].w0, din[u][s] - dout[u][s], d[s]);
     }
     for (; i < p.n_spans; ++i) {
         const DevSpan sp = load_span(spans, i);
-        const int ia = la + sp.lane_off, ib = lb + sp.c0;
+        const float* base = lane_lds + g.uni_part(sp.lane_off, lb + sp.c0);
+        const float* bin = base + (sp.len - 1) * st;
 #pragma unroll
         for (int s = 0; s < S; ++s)
-            if (s >= s_first)
-                d[s] = fmaf(sp.w0, lds[g.idx(ia, ib + s + sp.len - 1)] - lds[g.idx(ia, ib + s - 1)],
-                            d[s]);
+            d[s] = fmaf(sp.w0, bin[s * st] - base[(s == 0 ? z0 - 1 : s - 1) * st], d[s]);
     }
+    if (z0) d[0] = 0.f;
     // prefix of the changes inside the strip (value P, compensation C: true sum = P - C)
     float P[S], C[S];
     {
@@ -695,11 +714,11 @@ __device__ __forceinline__ void strip_sum(const float* src, int pitch, int a, in
     for (int i = 0; i < n; ++i) {
         const DevSpan sp = load_span(spans, i);
         const ConstFloatPtr wp = wts + sp.woff;
-        const int ia = a + sp.lane_off, ib = b + sp.c0;
+        const float* base = src + g.idx(a + sp.lane_off, b + sp.c0);
         switch (sp.len) {
 #define RL_PIECE(m) \
     case m:         \
-        if (m <= LMAX) span_piece<ORIENT_ROWS, S, (m <= LMAX ? m : 1)>(src, g, ia, ib, wp, part); \
+        if (m <= LMAX) span_piece<ORIENT_ROWS, S, (m <= LMAX ? m : 1)>(base, g, wp, part); \
         break;
             RL_PIECE(1) RL_PIECE(2) RL_PIECE(3) RL_PIECE(4) RL_PIECE(5) RL_PIECE(6)
             RL_PIECE(7) RL_PIECE(8) RL_PIECE(9) RL_PIECE(10) RL_PIECE(11) RL_PIECE(12)
