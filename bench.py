@@ -48,6 +48,43 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Algorithmic HBM bytes per output of one phase kernel: phase A reads u^k and f and writes
+# r; phase B reads r and u^k and writes u^{k+1} (float32 each).  Halo re-reads are not
+# algorithmic.  The resident box solver reads u and f and writes u once per launch.
+BYTES_PER_PX_PHASE = 12.0
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "phase-kernels-1024_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_7211_amd", "csrc", n)
+                  for n in ("rl_kernels.hpp", "rl_api.hip", "psf_compile.cpp", "psf_compile.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES:
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of kernel `name` (timing-registry name) from the committed
+    rocprofv3 counter summary, or None if there is none or the kernel sources changed
+    since the counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    a = text.find("```json")
+    if a < 0:
+        return None
+    b = text.find("```", a + 7)
+    data = json.loads(text[a + 7:b])
+    if data.get("source_sha256") != kernel_source_hash():
+        return None
+    return data.get("bytes_per_launch", {}).get(name)
+
+
 def algorithmic_flops_per_px(kind, info, phase_b):
     """Flops of the paper's algorithm for one output of one phase kernel.
 
@@ -76,7 +113,20 @@ def main():
                     help="also time the other mode (reported as 'other_mode')")
     ap.add_argument("--report", type=int, choices=[3, 4, 5], default=None)
     ap.add_argument("--requests", type=int, default=48, help="--report 5: requests")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (the "
+                         "reference dispatch for scaling HBM counters)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: turn two rocprofv3 --pmc CSV outputs (FETCH_SIZE, "
+                         "WRITE_SIZE) of a run with --calibrate-copy into the traffic "
+                         "summary (markdown) on stdout")
+    ap.add_argument("--pmc-command", default="",
+                    help="--summarize-pmc: the profiled command, quoted in the summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
+                            args.calibrate_copy, args.pmc_command))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the jobs are independent per GPU: N GPUs run N disjoint job sets)",
@@ -91,6 +141,14 @@ def main():
 
     A.lib()  # fail loudly if the HIP library is not built
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.report:
         line = {3: report_thinned, 4: report_batched, 5: report_serving}[args.report](args, dev)
         print(json.dumps(line), flush=True)
@@ -199,12 +257,26 @@ def main():
             else:
                 units = npx
             fl = algorithmic_flops_per_px(kind, inf, dom.endswith("update")) * units
-            achieved = fl / (kinfo["avg_us"] * 1e-6) / 1e12
-            roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP32_TFLOPS,
-                            unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 5),
-                            traffic=None, kernel=dom, job=jname,
-                            avg_us=round(kinfo["avg_us"], 3),
-                            flops_per_launch=fl)
+            by = BYTES_PER_PX_PHASE * npx
+            # roofline: the bound is the resource whose peak gives the longer minimum time
+            t_alu = fl / (PEAK_FP32_TFLOPS * 1e12)
+            t_hbm = by / (PEAK_HBM_GBS * 1e9)
+            dt = kinfo["avg_us"] * 1e-6
+            tr = measured_traffic(dom)
+            if t_hbm >= t_alu:
+                achieved = by / dt / 1e9
+                roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS,
+                                unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 5),
+                                traffic=tr)
+            else:
+                achieved = fl / dt / 1e12
+                roofline = dict(bound="alu", achieved=round(achieved, 4),
+                                peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                                frac=round(achieved / PEAK_FP32_TFLOPS, 5), traffic=tr)
+            roofline.update(kernel=dom, job=jname, avg_us=round(kinfo["avg_us"], 3),
+                            bytes_per_launch=by, flops_per_launch=fl,
+                            alu_frac=round(fl / dt / 1e12 / PEAK_FP32_TFLOPS, 5),
+                            hbm_frac=round(by / dt / 1e9 / PEAK_HBM_GBS, 5))
     log(f"bench: kernels {json.dumps(kernels)}")
 
     cpu = None
@@ -415,6 +487,77 @@ def report_serving(args, dev):
         "plain_per_image": dict(latency=rep_p, wall_s=dt_p, px_it_per_s=px_it / dt_p),
         "results_identical": bool(same),
     }
+
+
+def _timing_name(kernel):
+    """Map a rocprofv3 kernel symbol to the library's timing-registry name."""
+    import re
+    m = re.search(r"rlk::(slide|span|resident)_kernel<([^>]*)>", kernel)
+    if not m:
+        return None
+    kind, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if kind == "resident":
+        return "resident_box"
+    phase_b = targs[-1] == "true"
+    if kind == "span" and targs[2] == "1":
+        kind = "direct"
+    return f"{kind}_{'corr_update' if phase_b else 'conv_ratio'}"
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_mib, command):
+    """Per-kernel HBM traffic (KiB per dispatch, averaged) from two rocprofv3 --pmc runs,
+    scaled by the ratio of the known size of the calibration copy to what the same
+    counter reads for it."""
+    import csv
+    import glob
+    import hashlib
+
+    def read(d, counter):
+        fn = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        per = {}
+        for r in csv.DictReader(open(fn)):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch = read(fetch_dir, "FETCH_SIZE")
+    write = read(write_dir, "WRITE_SIZE")
+    known = copy_mib * 1024.0  # KiB read and written by the calibration copy
+    # the calibration copy is the non-library dispatch that reads the most
+    others = [k for k in fetch if "rlk::" not in k and k in write]
+    cal = max(others, key=lambda k: max(fetch[k]))
+    f_cal, w_cal = max(fetch[cal]), max(write[cal])
+    sf, sw = known / f_cal, known / w_cal
+    rows, per_launch = [], {}
+    for k in sorted(set(fetch) | set(write)):
+        fv, wv = fetch.get(k, [0.0]), write.get(k, [0.0])
+        fa, wa = sum(fv) / len(fv), sum(wv) / len(wv)
+        name = _timing_name(k)
+        rows.append((k, len(fv), fa, wa, name))
+        if name:
+            per_launch[name] = round((fa * sf + wa * sw) * 1024.0)
+    src_hash = kernel_source_hash()
+    out = ["# HBM traffic counters: phase kernels of the specialised-PSF workload "
+           "(3 x 1024x1024, 20 iterations, batch mode)", "",
+           "Commands (one counter per run; rocprofv3 does not split counters over passes):", "",
+           "```", command.strip(), "```", "",
+           f"Values are KiB per dispatch, averaged over dispatches.  Calibration: a plain "
+           f"device-to-device copy of {copy_mib} MiB (`{cal[:60]}`) reads FETCH_SIZE "
+           f"{f_cal:.1f} KiB and WRITE_SIZE {w_cal:.1f} KiB for {known:.0f} KiB moved each "
+           f"way: scale factors fetch {sf:.4f}, write {sw:.4f}.", "",
+           "| Kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled total MiB | registry name |",
+           "|---|---|---|---|---|---|"]
+    for k, n, fa, wa, name in rows:
+        out.append(f"| `{k[:90]}` | {n} | {fa:.1f} | {wa:.1f} | "
+                   f"{(fa * sf + wa * sw) / 1024:.2f} | {name or ''} |")
+    out += ["", "Algorithmic traffic of one phase launch at 1024 x 1024: 12 B per pixel "
+            "(two float32 planes read, one written) = 12.0 MiB.", "",
+            "Machine-readable (bench.py reports `bytes_per_launch` as roofline.traffic while "
+            "the kernel sources hash to `source_sha256`):", "", "```json",
+            json.dumps(dict(source_sha256=src_hash, scale=dict(fetch=sf, write=sw),
+                            bytes_per_launch=per_launch), indent=1), "```"]
+    return "\n".join(out)
 
 
 def cpu_baseline(jobs):

@@ -2,6 +2,7 @@
 // Every RL step runs in the kernels of rl_kernels.hpp; this file only decides which kernel,
 // with which tables and tiles, and enqueues them on the job's stream.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <map>
@@ -458,24 +459,31 @@ hipError_t launch(const char* name, void (*kernel)(KArgs...), dim3 grid, dim3 bl
         std::lock_guard<std::mutex> g(g_tmu);
         timed = g_timing;
     }
-    if (timed) {
-        (void)hipEventCreate(&tl.a);
-        (void)hipEventCreate(&tl.b);
-        (void)hipEventRecord(tl.a, s);
-    }
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
-    hipError_t e = hipGetLastError();
-    if (timed) {
-        (void)hipEventRecord(tl.b, s);
-        tl.name = name;
-        std::lock_guard<std::mutex> g(g_tmu);
-        g_timed.push_back(tl);
+    if (!timed) {
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+        return hipGetLastError();
     }
+    // Timed: the start and stop events travel with the dispatch packet itself
+    // (hipExtLaunchKernel), so they bracket the kernel's execution and not the queueing of
+    // separate event packets around it.
+    (void)hipEventCreate(&tl.a);
+    (void)hipEventCreate(&tl.b);
+    std::tuple<KArgs...> targs(args...);
+    void* argv[sizeof...(KArgs)];
+    std::apply([&](auto&... a) {
+        int i = 0;
+        ((argv[i++] = static_cast<void*>(&a)), ...);
+    }, targs);
+    hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv,
+                                      lds, s, tl.a, tl.b, 0);
+    tl.name = name;
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_timed.push_back(tl);
     return e;
 }
 
