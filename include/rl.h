@@ -71,6 +71,10 @@ typedef int32_t rl_status;
 #define RL_SCHED_FUSED 3    /* one kernel per iteration: conv, ratio, corr and update on an
                                LDS tile with a double halo (u double-buffered); plain jobs
                                with height, width >= 64 and PSF extents <= 63 only         */
+#define RL_SCHED_PERSISTENT 4 /* reserved: one launch per rl_iterate call running both
+                               phases of every iteration, tiles synchronised through
+                               per-tile step counters.  Currently switched off: every
+                               call asking for it returns RL_E_UNSUPPORTED.              */
 
 /* thinning (Section 4) */
 #define RL_THIN_OFF 0

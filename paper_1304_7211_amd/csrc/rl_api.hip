@@ -50,6 +50,7 @@ std::vector<TimedLaunch> g_timed;
 struct Config {
     int path = 0, sched = 0, kind = 0, orient = 0, S = 16, lmax = 1;
     int TA = 64, TB = 64, tiles_a = 1, tiles_b = 1;
+    int reach_a = 1, reach_b = 1;  // persistent schedule: tiles within the halo's reach
     // resident
     int line_n = 0, lines = 0, wpl = 1, seg = 2, lines_per_wg = 1, line_words = 0;
     size_t lds_a = 0, lds_b = 0;
@@ -58,7 +59,7 @@ struct Config {
 
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
-        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, total;
+        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, total;
 };
 
 // counters block (int64 slots)
@@ -184,7 +185,12 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     }
     cfg->path = path;
     int sched = p->schedule;
-    if (sched < RL_SCHED_AUTO || sched > RL_SCHED_FUSED) { *why = "unknown schedule"; return RL_E_INVAL; }
+    if (sched < RL_SCHED_AUTO || sched > RL_SCHED_PERSISTENT) { *why = "unknown schedule"; return RL_E_INVAL; }
+    if (sched == RL_SCHED_PERSISTENT) {
+        // Switched off: its first GPU run did not finish, and no cause has been shown yet.
+        *why = "the persistent schedule is switched off";
+        return RL_E_UNSUPPORTED;
+    }
     if (sched == RL_SCHED_FUSED) {
         if (thin) { *why = "the fused schedule serves plain RL"; return RL_E_UNSUPPORTED; }
         if (H < 64 || W < 64) { *why = "the fused schedule needs images of at least 64 x 64"; return RL_E_UNSUPPORTED; }
@@ -214,7 +220,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         return RL_OK;
     }
     const int box_orient = c.box_orient == rl::Orient::Rows ? rlk::ORIENT_ROWS : rlk::ORIENT_COLS;
-    if (path == RL_PATH_BOX_AXIS && !thin && sched != RL_SCHED_TWO_PASS) {
+    if (path == RL_PATH_BOX_AXIS && !thin && (sched == RL_SCHED_AUTO || sched == RL_SCHED_RESIDENT)) {
         int n = box_orient == rlk::ORIENT_ROWS ? W : H;
         int m = box_orient == rlk::ORIENT_ROWS ? H : W;
         // the on-chip halo holds a single reflection: needs L - 1 <= line length
@@ -257,7 +263,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         *why = "the resident schedule serves BOX_AXIS PSFs without thinning";
         return RL_E_UNSUPPORTED;
     }
-    cfg->sched = RL_SCHED_TWO_PASS;
+    cfg->sched = sched == RL_SCHED_PERSISTENT ? RL_SCHED_PERSISTENT : RL_SCHED_TWO_PASS;
     const float* h = p->psf;
     const int kh = p->psf_h, kw = p->psf_w;
     const bool kahan = p->kahan != 0;
@@ -356,6 +362,16 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     const int lb = cfg->orient == rlk::ORIENT_ROWS ? W : H;
     cfg->tiles_a = (la + cfg->TA - 1) / cfg->TA;
     cfg->tiles_b = (lb + cfg->TB - 1) / cfg->TB;
+    if (cfg->sched == RL_SCHED_PERSISTENT) {
+        if (cfg->S != 4 && cfg->S != 8) { *why = "the persistent schedule runs strips of 4 or 8"; return RL_E_UNSUPPORTED; }
+        // tiles whose data a tile's halo can reach, on each axis; a fold deeper than the
+        // image can reach anywhere on that axis
+        const rl::OpTable &v = cfg->conv, &c2 = cfg->corr;
+        const int ha = std::max({-v.lane_min, v.lane_max, -c2.lane_min, c2.lane_max, 0});
+        const int hb = std::max({-v.c_min, v.c_max, -c2.c_min, c2.c_max, 0});
+        cfg->reach_a = ha >= la ? cfg->tiles_a : (ha + cfg->TA - 1) / cfg->TA;
+        cfg->reach_b = hb >= lb ? cfg->tiles_b : (hb + cfg->TB - 1) / cfg->TB;
+    }
     return RL_OK;
 }
 
@@ -391,6 +407,8 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     L.prefix = take(2 * sizeof(int32_t));
     L.red = take(rlk::RED_BLOCKS * 8);
     L.red_i = take(rlk::RED_BLOCKS * 8);
+    L.done = cfg.sched == RL_SCHED_PERSISTENT ? take(ntiles * 4) : 0;
+    L.pctl = take(2 * sizeof(int32_t));  // persistent launches: ticket, abort flag
     L.total = o;
     return L;
 }
@@ -432,6 +450,7 @@ struct rl_job {
     hipGraphExec_t graph = nullptr;  // captured chunk of graph_iters plain iterations
     int graph_n = 0;
     int graph_par = 0;  // parity of k the captured chunk starts at (fused schedule)
+    bool persist_used = false;  // a persistent launch ran: check its abort flag
     // the plane holding u^k: the fused schedule alternates between u and u2
     float* cur_u() const {
         return (cfg.kind == KIND_FUSED && (k & 1)) ? reinterpret_cast<float*>(ws + L.u2)
@@ -526,6 +545,53 @@ PhaseFn slide_fn(int S) {
     }
     return nullptr;
 }
+
+using PersistFn = void (*)(rlk::PersistArgs);
+
+template <int K, int O, int S>
+PersistFn persist_fn_l(int lmax) {
+    if (K == KIND_SLIDE) return rlk::persist_kernel<KIND_SLIDE, O, S, 1, kNW>;
+    switch (lmax) {
+        case 1: return rlk::persist_kernel<KIND_SPAN, O, S, 1, kNW>;
+        case 4: return rlk::persist_kernel<KIND_SPAN, O, S, 4, kNW>;
+        case 8: return rlk::persist_kernel<KIND_SPAN, O, S, 8, kNW>;
+        case 16: return rlk::persist_kernel<KIND_SPAN, O, S, 16, kNW>;
+    }
+    return nullptr;
+}
+
+template <int K, int O>
+PersistFn persist_fn_s(int S, int lmax) {
+    switch (S) {
+        case 4: return persist_fn_l<K, O, 4>(lmax);
+        case 8: return persist_fn_l<K, O, 8>(lmax);
+    }
+    return nullptr;
+}
+
+PersistFn persist_fn(const Config& c) {
+    if (c.kind == KIND_SPAN)
+        return c.orient == rlk::ORIENT_ROWS ? persist_fn_s<KIND_SPAN, rlk::ORIENT_ROWS>(c.S, c.lmax)
+                                            : persist_fn_s<KIND_SPAN, rlk::ORIENT_COLS>(c.S, c.lmax);
+    return c.orient == rlk::ORIENT_ROWS ? persist_fn_s<KIND_SLIDE, rlk::ORIENT_ROWS>(c.S, 0)
+                                        : persist_fn_s<KIND_SLIDE, rlk::ORIENT_COLS>(c.S, 0);
+}
+
+// Workgroups of a persistent kernel that the device holds at once.
+int persist_capacity(PersistFn fn, size_t lds) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                     kNW * 64, lds) != hipSuccess)
+        return 0;
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+
+constexpr int kSpinLimit = 1 << 22;  // polls before a persistent launch gives up
 
 PhaseFn phase_fn(const Config& c, bool phase_b) {
     if (c.kind == KIND_SPAN) {
@@ -737,6 +803,48 @@ rl_status enqueue_iterations(rl_job* j, int32_t n) {
 rl_status enqueue_direct(rl_job* j, int32_t n) {
     const Config& c = j->cfg;
     hipStream_t s = j->stream;
+    if (c.sched == RL_SCHED_PERSISTENT) {
+        if (n == 0) return RL_OK;
+        const int ntiles = c.tiles_a * c.tiles_b;
+        int32_t* done = j->at<int32_t>(j->L.done);
+        int32_t* pctl = j->at<int32_t>(j->L.pctl);
+        rl_status st = dev_err(launch("fill", rlk::fill_u32_kernel, dim3(grid_for(ntiles)), dim3(256), 0,
+                                      s, (uint32_t*)done, 0u, (int64_t)ntiles), "fill");
+        if (st) return st;
+        // the ticket starts at 0; the abort flag (pctl[1]) is sticky for the job's life
+        st = dev_err(launch("fill", rlk::fill_u32_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)pctl,
+                            0u, (int64_t)1), "fill");
+        if (st) return st;
+        rlk::PersistArgs P{};
+        P.jobs = nullptr;
+        P.prefix = nullptr;
+        P.n_jobs = 1;
+        P.total_tiles = ntiles;
+        P.max_steps = 2 * n;
+        P.spin_limit = kSpinLimit;
+        P.ticket = pctl;
+        P.abort = pctl + 1;
+        P.one.a = phase_args(j, false, j->k);
+        P.one.b = phase_args(j, true, j->k);
+        P.one.done = done;
+        P.one.n_steps = 2 * n;
+        P.one.reach_a = c.reach_a;
+        P.one.reach_b = c.reach_b;
+        PersistFn fn = persist_fn(c);
+        if (!fn) return RL_E_UNSUPPORTED;
+        const size_t lds = std::max(c.lds_a, c.lds_b);
+        const int64_t tasks = (int64_t)2 * n * ntiles;
+        if (tasks > ((int64_t)1 << 30)) return RL_E_UNSUPPORTED;
+        const int cap = persist_capacity(fn, lds);
+        if (cap <= 0) return RL_E_DEVICE;
+        const unsigned grid = (unsigned)std::min<int64_t>(cap, tasks);
+        st = dev_err(launch(c.kind == KIND_SLIDE ? "persist_slide" : "persist_span", fn, dim3(grid),
+                            dim3(kNW * 64), lds, s, P), "persistent");
+        if (st) return st;
+        j->k += n;
+        j->persist_used = true;
+        return RL_OK;
+    }
     if (c.kind == KIND_FUSED) {
         const rlk::FusedArgs* table = j->at<rlk::FusedArgs>(j->L.fargs);
         for (int i = 0; i < n; ++i) {
@@ -943,6 +1051,7 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     if ((st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.u), p->u0 ? p->u0 : p->f, N), "copy u0"))) { delete j; return st; }
     if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(g), dim3(256), 0, s, j->at<uint32_t>(j->L.r), 0u, N), "zero r"))) { delete j; return st; }
     if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(1), dim3(256), 0, s, j->at<uint32_t>(j->L.ctr), 0u, (int64_t)C_COUNT * 2), "zero ctr"))) { delete j; return st; }
+    if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(1), dim3(256), 0, s, j->at<uint32_t>(j->L.pctl), 0u, (int64_t)2), "zero pctl"))) { delete j; return st; }
     if (p->thin.mode != RL_THIN_OFF) {
         int64_t nt = (int64_t)j->cfg.tiles_a * j->cfg.tiles_b;
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(N / 4 + 1)), dim3(256), 0, s, j->at<uint32_t>(j->L.cnt), 0u, (N + 3) / 4), "zero cnt"))) { delete j; return st; }
@@ -985,9 +1094,16 @@ rl_status rl_result(rl_job* j, float* u_out, rl_stats* st) {
                              (const double*)j->at<double>(j->L.red), thin ? (const int64_t*)j->at<int64_t>(j->L.red_i) : (const int64_t*)nullptr,
                              reinterpret_cast<double*>(ctr + C_FLUX), thin ? ctr + C_ACTIVE_NOW : (int64_t*)nullptr), "final"))) return rs;
     int64_t h[C_COUNT];
+    int32_t pc[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && j->persist_used)
+        e = hipMemcpyAsync(pc, j->at<int32_t>(j->L.pctl), sizeof pc, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if ((rs = dev_err(e, "read stats"))) return rs;
+    if (pc[1]) {
+        g_last_error = "a persistent launch exceeded its wait limit; the result is incomplete";
+        return RL_E_DEVICE;
+    }
     std::memset(st, 0, sizeof *st);
     st->iters_done = j->k;
     double flux;

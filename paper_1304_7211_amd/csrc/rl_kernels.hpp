@@ -469,13 +469,12 @@ __device__ __forceinline__ void span_piece(const float* base, const TileGeom<ORI
     }
 }
 
+// One output tile of a phase (span kernel): tile origin (a0, b0) on the lane and strip
+// axes; lds is the workgroup's dynamic LDS.  Shared by the per-phase kernel and the
+// persistent schedule.
 template <int ORIENT, int S, int LMAX, int NW, bool PHASE_B>
-__global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void span_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
     constexpr int TA = 64, TB = NW * S;
-    int a0, b0;
-    PhaseArgs p;
-    if (!resolve<PHASE_B>(L, p, TA, TB, a0, b0)) return;
     TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
@@ -525,6 +524,15 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
     write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, acc0, plan);
 }
 
+template <int ORIENT, int S, int LMAX, int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
+    extern __shared__ float lds[];
+    int a0, b0;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, 64, NW * S, a0, b0)) return;
+    span_tile<ORIENT, S, LMAX, NW, PHASE_B>(p, a0, b0, lds);
+}
+
 // ---------------------------------------------------------------------------------------
 // Sliding kernel (generic box filter): every span is a run of equal weights.  Moving the
 // output one step along the strip adds the entering tap and removes the leaving tap of each
@@ -539,12 +547,8 @@ template <int NW>
 __host__ __device__ constexpr int slide_scratch_floats() { return 4 * NW * 64; }
 
 template <int ORIENT, int S, int NW, bool PHASE_B>
-__global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
     constexpr int TA = 64, TB = NW * S;
-    int a0, b0;
-    PhaseArgs p;
-    if (!resolve<PHASE_B>(L, p, TA, TB, a0, b0)) return;
     TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
     EpiPlan<ORIENT, S, NW> plan;
     epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
@@ -656,6 +660,158 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
 #pragma unroll
     for (int s = 0; s < S; ++s) out[s] = b_true + (P[s] - C[s]);
     write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, out, plan);
+}
+
+template <int ORIENT, int S, int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
+    extern __shared__ float lds[];
+    int a0, b0;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, 64, NW * S, a0, b0)) return;
+    slide_tile<ORIENT, S, NW, PHASE_B>(p, a0, b0, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// Persistent schedule (plain RL): one launch runs every phase of every iteration of one or
+// more jobs.  A task is (step s, tile t) with step s = 2 (k - k0) + phase; tasks are
+// numbered step by step (q = s * total_tiles + tile index) and handed out in that order by
+// an atomic ticket, so a workgroup only ever waits for tasks with smaller numbers, which
+// running workgroups hold or have finished: the schedule cannot deadlock, whatever the
+// number of resident workgroups.  Task (s, t) waits until every tile within the phase
+// halo's reach has finished step s - 1 (done[t'] >= s): that covers the data it reads
+// (u^k from phase B, or r from phase A) and the data it overwrites (which those tiles read
+// in step s - 1).  Completion: every wavefront waits for its stores, the workgroup
+// synchronises, and one lane publishes done[t] = s + 1 after an agent-scope release (the
+// XCDs have separate L2 caches); the waiting side polls with relaxed agent-scope loads and
+// then takes an agent-scope acquire before reading.  Waits are bounded: past spin_limit
+// polls the launch raises *abort and every workgroup leaves, so the kernel always ends.
+// ---------------------------------------------------------------------------------------
+struct PersistJob {
+    PhaseArgs a, b;        // phase A / phase B records (k = iteration index at launch)
+    int32_t* done;         // per tile: steps finished in this launch (zero at launch)
+    int32_t n_steps;       // 2 x iterations of this job in this launch
+    int32_t reach_a, reach_b;  // tiles within the halo reach on each axis
+    int32_t pad;
+};
+
+struct PersistArgs {
+    const PersistJob* jobs;   // n_jobs entries (device); unused when n_jobs == 1
+    const int32_t* prefix;    // tile prefix over jobs (n_jobs + 1)
+    int32_t n_jobs, total_tiles, max_steps, spin_limit;
+    int32_t* ticket;          // zero at launch
+    int32_t* abort;           // zero at launch; set when a wait exceeded spin_limit
+    PersistJob one;           // the job itself when n_jobs == 1
+};
+
+typedef const __attribute__((address_space(4))) PersistJob* ConstPersistPtr;
+
+__device__ __forceinline__ PersistJob load_persist(ConstPersistPtr t) {
+    PersistJob j;
+    j.a = load_args((ConstArgsPtr)&t->a);
+    j.b = load_args((ConstArgsPtr)&t->b);
+    j.done = t->done;
+    j.n_steps = t->n_steps;
+    j.reach_a = t->reach_a;
+    j.reach_b = t->reach_b;
+    j.pad = 0;
+    return j;
+}
+
+__device__ __forceinline__ int poll_done(int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: wait until every tile in the reach of tile t has finished step s - 1.
+// Returns false if the launch is being aborted.
+__device__ __forceinline__ bool wait_deps(const PersistJob& J, int t, int s, int spin_limit,
+                                          int32_t* abort) {
+    if (s == 0) return true;
+    const int ta_n = J.a.tiles_a, tb_n = J.a.tiles_b;
+    const int ta = t % ta_n, tb = t / ta_n;
+    const int a_lo = max(0, ta - J.reach_a), a_hi = min(ta_n - 1, ta + J.reach_a);
+    const int b_lo = max(0, tb - J.reach_b), b_hi = min(tb_n - 1, tb + J.reach_b);
+    int spins = 0;
+    for (int y = b_lo; y <= b_hi; ++y) {
+        for (int x = a_lo; x <= a_hi; ++x) {
+            int32_t* d = J.done + y * ta_n + x;
+            while (poll_done(d) < s) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > spin_limit) {
+                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    return false;
+                }
+                if ((spins & 1023) == 0 && poll_done(abort)) return false;
+            }
+        }
+    }
+    return true;
+}
+
+template <int KIND, int ORIENT, int S, int LMAX, int NW>
+__global__ __launch_bounds__(NW * 64) void persist_kernel(PersistArgs P) {
+    extern __shared__ float lds[];
+    __shared__ int32_t task[3];  // job, tile, step (job < 0: leave)
+    constexpr int TA = 64, TB = NW * S;
+    const int64_t total = (int64_t)P.max_steps * P.total_tiles;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int q = atomicAdd(P.ticket, 1);
+            int jn = -1, t = 0, st = 0;
+            if (q < total && !poll_done(P.abort)) {
+                st = q / P.total_tiles;
+                const int idx = q - st * P.total_tiles;
+                int lo = 0;
+                if (P.n_jobs > 1) {
+                    const ConstIntPtr pre = (ConstIntPtr)P.prefix;
+                    int hi = P.n_jobs - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (pre[mid] <= idx) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    t = idx - pre[lo];
+                } else {
+                    t = idx;
+                }
+                jn = lo;
+                const PersistJob J = P.n_jobs > 1 ? load_persist((ConstPersistPtr)P.jobs + lo) : P.one;
+                if (st >= J.n_steps) {
+                    jn = -2;  // this job has no step st: nothing to do
+                } else if (!wait_deps(J, t, st, P.spin_limit, P.abort)) {
+                    jn = -1;
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+            }
+            task[0] = jn;
+            task[1] = t;
+            task[2] = st;
+        }
+        __syncthreads();
+        const int jn = task[0], t = task[1], st = task[2];
+        __syncthreads();  // task[] is rewritten at the next loop top
+        if (jn == -1) break;
+        if (jn == -2) continue;
+        const PersistJob J = P.n_jobs > 1 ? load_persist((ConstPersistPtr)P.jobs + jn) : P.one;
+        const bool phase_b = (st & 1) != 0;
+        PhaseArgs p = phase_b ? J.b : J.a;
+        p.k += st >> 1;
+        p.full = 1;
+        const int a0 = (t % p.tiles_a) * TA, b0 = (t / p.tiles_a) * TB;
+        if (KIND == 0) {
+            if (phase_b) span_tile<ORIENT, S, LMAX, NW, true>(p, a0, b0, lds);
+            else span_tile<ORIENT, S, LMAX, NW, false>(p, a0, b0, lds);
+        } else {
+            if (phase_b) slide_tile<ORIENT, S, NW, true>(p, a0, b0, lds);
+            else slide_tile<ORIENT, S, NW, false>(p, a0, b0, lds);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // this wavefront's stores have reached L2
+        __syncthreads();                // every wavefront's have; LDS is free again
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // visible to every XCD
+            __hip_atomic_store(J.done + t, st + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------

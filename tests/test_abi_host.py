@@ -128,6 +128,11 @@ def test_workspace_bytes_and_validation(A):
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
     p, k9 = _params(A, psf=synth.box_h(9), schedule=A.RL_SCHED_RESIDENT)
     assert _ws_status(A, p)[0] == A.RL_OK
+    # the persistent schedule is switched off
+    p, k10 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT)
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k11 = _params(A, schedule=9)
+    assert _ws_status(A, p)[0] == A.RL_E_INVAL
 
 
 def test_null_and_state_errors(A):
