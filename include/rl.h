@@ -88,6 +88,9 @@ typedef struct rl_thin {
     int32_t reset_period;   /* R: iteration k is full when k == 0 or k % R == 0; 0 = never */
     int32_t compact_period; /* C: the active list is rebuilt after each full step and when
                                (k - 1) % C == 0                                           */
+    int32_t keep_list;      /* 1: also build the per-pixel active list at every rebuild
+                               (exported by rl_active_list); 0: only the tile list that
+                               distributes the work is built                              */
 } rl_thin;
 
 /* Kernel-shape and launch knobs (0 = let the library choose).  Results do not depend on
@@ -202,7 +205,8 @@ rl_status rl_set_state(rl_job *job, const float *u, const float *r, const uint8_
 /*
  * Thinned mode: the compacted active-pixel list of the last rebuild (ascending row-major
  * indices p with cnt[p] < hysteresis, Section 4), copied into list_dev (device int32,
- * capacity cap entries); *n receives the list length (synchronises the stream).
+ * capacity cap entries); *n receives the list length (synchronises the stream), or -1
+ * if there is no list: no rebuild yet, or the job was created with thin.keep_list = 0.
  */
 rl_status rl_active_list(rl_job *job, int32_t *list_dev, int64_t cap, int64_t *n);
 

@@ -36,7 +36,7 @@ EXPORTS = ["rl_status_str", "rl_workspace_bytes", "rl_init", "rl_iterate", "rl_r
 class rl_thin(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float),
                 ("hysteresis", ctypes.c_int32), ("reset_period", ctypes.c_int32),
-                ("compact_period", ctypes.c_int32)]
+                ("compact_period", ctypes.c_int32), ("keep_list", ctypes.c_int32)]
 
 
 class rl_tuning(ctypes.Structure):

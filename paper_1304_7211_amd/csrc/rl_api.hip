@@ -451,6 +451,11 @@ struct rl_job {
     int graph_n = 0;
     int graph_par = 0;  // parity of k the captured chunk starts at (fused schedule)
     bool persist_used = false;  // a persistent launch ran: check its abort flag
+    // thinned jobs: asynchronous readback of the active-tile count after each rebuild
+    int64_t* h_tcount = nullptr;  // pinned host word
+    hipEvent_t tc_event = nullptr;
+    bool tc_pending = false;
+    int64_t tc_known = -1;        // last count that reached the host (-1: none yet)
     // the plane holding u^k: the fused schedule alternates between u and u2
     float* cur_u() const {
         return (cfg.kind == KIND_FUSED && (k & 1)) ? reinterpret_cast<float*>(ws + L.u2)
@@ -653,6 +658,7 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     a.tiles_b = c.tiles_b;
     a.k = k0;
     a.full = 1;
+    a.list_ok = 1;
     if (j->p.thin.mode != RL_THIN_OFF) {
         a.cnt = j->at<uint8_t>(j->L.cnt);
         a.thin_mode = j->p.thin.mode;
@@ -687,15 +693,38 @@ rl_status rebuild_lists(rl_job* j, hipStream_t s) {
     a.n_blocks = nb;
     rl_status st;
     if ((st = dev_err(launch("thin_count", rlk::thin_count_kernel, dim3(nb), dim3(256), 0, s, a), "thin_count"))) return st;
-    if ((st = dev_err(launch("thin_scan", rlk::scan_counts_kernel, dim3(1), dim3(1024), 0, s,
-                             (const int32_t*)a.block_counts, a.block_offsets, nb, a.plist_len), "thin_scan"))) return st;
-    if ((st = dev_err(launch("thin_scatter", rlk::thin_scatter_kernel, dim3(nb), dim3(256), 0, s, a), "thin_scatter"))) return st;
+    if (j->p.thin.keep_list) {
+        if ((st = dev_err(launch("thin_scan", rlk::scan_counts_kernel, dim3(1), dim3(1024), 0, s,
+                                 (const int32_t*)a.block_counts, a.block_offsets, nb, a.plist_len), "thin_scan"))) return st;
+        if ((st = dev_err(launch("thin_scatter", rlk::thin_scatter_kernel, dim3(nb), dim3(256), 0, s, a), "thin_scatter"))) return st;
+    }
     int ntiles = j->cfg.tiles_a * j->cfg.tiles_b;
+    int64_t* tcount = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
     if ((st = dev_err(launch("tile_compact", rlk::tile_compact_kernel, dim3(1), dim3(1024), 0, s,
-                             a.tflag, ntiles, j->at<int32_t>(j->L.tlist),
-                             j->at<int64_t>(j->L.ctr) + C_TLIST_LEN), "tile_compact"))) return st;
+                             a.tflag, ntiles, j->at<int32_t>(j->L.tlist), tcount), "tile_compact"))) return st;
     j->list_valid = true;
+    // Read the active-tile count back without waiting: a later iteration uses it (once the
+    // copy has landed) to skip the tile list when nearly every tile is active.
+    if (j->h_tcount && j->tc_event) {
+        hipError_t e = hipMemcpyAsync(j->h_tcount, tcount, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(j->tc_event, s);
+        if ((st = dev_err(e, "tile count readback"))) return st;
+        j->tc_pending = true;
+    }
     return RL_OK;
+}
+
+// Whether non-full thinned steps should go through the tile list: yes unless the last
+// active-tile count that has reached the host shows (almost) every tile active, in which
+// case all tiles run and the per-pixel test in the epilogue alone skips frozen pixels
+// (the same arithmetic either way).
+bool use_tile_list(rl_job* j) {
+    if (j->tc_pending && hipEventQuery(j->tc_event) == hipSuccess) {
+        j->tc_known = *j->h_tcount;
+        j->tc_pending = false;
+    }
+    const int64_t ntiles = (int64_t)j->cfg.tiles_a * j->cfg.tiles_b;
+    return j->tc_known < 0 || j->tc_known * 10 < ntiles * 9;
 }
 
 rl_status enqueue_iterations(rl_job* j, int32_t n);
@@ -876,6 +905,7 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
             if (st) return st;
         }
         la.kb = lb.kb = j->k;
+        if (thin) la.one.list_ok = lb.one.list_ok = use_tile_list(j) ? 1 : 0;
         rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, la), na);
         if (st) return st;
         st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lb), nbn);
@@ -937,6 +967,48 @@ std::vector<DevSpan> to_dev(const rl::OpTable& t) {
     if (!t.spans.empty()) std::memcpy(v.data(), t.spans.data(), v.size() * sizeof(DevSpan));
     if (v.empty()) v.resize(1);
     return v;
+}
+
+}  // namespace
+
+namespace {  // autotuner helpers
+
+// Candidate (schedule, tuning) pairs for a job's kernel family.
+std::vector<TuneEntry> tune_candidates(const rl_params* p, const Config& base) {
+    std::vector<TuneEntry> v;
+    auto add = [&](int sched, int strip, int seg, int lpw, int gi) {
+        TuneEntry e{};
+        e.schedule = p->schedule == RL_SCHED_AUTO ? sched : p->schedule;
+        e.t.strip = strip;
+        e.t.seg = seg;
+        e.t.lines_per_wg = lpw;
+        e.t.graph_iters = gi;
+        v.push_back(e);
+    };
+    const bool thin = p->thin.mode != RL_THIN_OFF;
+    if (base.kind == KIND_RESIDENT) {
+        for (int seg : {4, 8, 16})
+            for (int lpw : {1, 2, 4}) add(RL_SCHED_RESIDENT, 0, seg, lpw, 0);
+        return v;
+    }
+    const int gi = thin ? 0 : 16;
+    for (int strip : {4, 8, 16}) {
+        add(RL_SCHED_TWO_PASS, strip, 0, 0, 0);
+        if (gi) add(RL_SCHED_TWO_PASS, strip, 0, 0, gi);
+    }
+    if (base.kind == KIND_SLIDE) add(RL_SCHED_TWO_PASS, 32, 0, 0, gi);
+    if (!thin && p->schedule == RL_SCHED_AUTO) {
+        add(RL_SCHED_FUSED, 0, 0, 0, 0);
+        add(RL_SCHED_FUSED, 0, 0, 0, gi);
+    }
+    return v;
+}
+
+rl_params with_entry(const rl_params* p, const TuneEntry& e) {
+    rl_params q = *p;
+    q.tuning = e.t;
+    q.schedule = e.schedule;
+    return q;
 }
 
 }  // namespace
@@ -1061,6 +1133,17 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     }
     if ((st = dev_err(launch("check_f", rlk::check_f_kernel, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s,
                              (const float*)j->at<float>(j->L.f), N, reinterpret_cast<int32_t*>(j->at<int64_t>(j->L.ctr) + C_F_INVALID)), "check f"))) { delete j; return st; }
+    if (p->thin.mode != RL_THIN_OFF) {
+        // pinned word and event for the asynchronous active-tile count (optional: without
+        // them the tile list is always used)
+        if (hipHostMalloc((void**)&j->h_tcount, sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+            j->h_tcount = nullptr;
+        if (j->h_tcount && hipEventCreateWithFlags(&j->tc_event, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(j->h_tcount);
+            j->h_tcount = nullptr;
+            j->tc_event = nullptr;
+        }
+    }
     *out = j;
     return RL_OK;
 }
@@ -1129,6 +1212,11 @@ rl_status rl_destroy(rl_job* j) {
     if (!j->live) return RL_E_STATE;
     j->live = false;
     if (j->graph) (void)hipGraphExecDestroy(j->graph);
+    if (j->tc_event) {
+        if (j->tc_pending) (void)hipEventSynchronize(j->tc_event);  // copy into h_tcount
+        (void)hipEventDestroy(j->tc_event);
+    }
+    if (j->h_tcount) (void)hipHostFree(j->h_tcount);
     delete j;
     return RL_OK;
 }
@@ -1221,6 +1309,8 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
                 rl_job* j = jobs[g.idx[q]];
                 ta[q] = phase_args(j, false, j->k);
                 tb[q] = phase_args(j, true, j->k);
+                if (j->p.thin.mode != RL_THIN_OFF)
+                    ta[q].list_ok = tb[q].list_ok = use_tile_list(j) ? 1 : 0;
             }
             std::memcpy(bs.host.data() + g.off_p, g.prefix.data(), g.prefix.size() * sizeof(int32_t));
         }
@@ -1273,6 +1363,7 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
                 if (m == 1) {
                     rl_job* j1 = jobs[g.idx[0]];
                     la.one = phase_args(j1, phase == 1, j1->k);
+                    if (j1->p.thin.mode != RL_THIN_OFF) la.one.list_ok = use_tile_list(j1) ? 1 : 0;
                 }
                 st = dev_err(launch(phase ? g.nb : g.na, phase ? g.fb : g.fa, dim3(g.prefix[m]),
                                     dim3(kNW * 64), phase ? g.lds_b : g.lds_a, gsm, la),
@@ -1339,8 +1430,9 @@ rl_status rl_active_list(rl_job* j, int32_t* list_dev, int64_t cap, int64_t* n) 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     rl_status st = dev_err(e, "list len");
     if (st) return st;
-    *n = j->list_valid ? len : -1;
-    if (list_dev && len > 0 && j->list_valid) {
+    const bool have = j->list_valid && j->p.thin.keep_list;
+    *n = have ? len : -1;
+    if (list_dev && len > 0 && have) {
         if (cap < len) return RL_E_NOMEM;
         e = hipMemcpyAsync(list_dev, j->at<int32_t>(j->L.plist), (size_t)len * 4, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1424,47 +1516,6 @@ rl_status rl_timing_reset(void) {
     return RL_OK;
 }
 
-namespace {
-
-// Candidate (schedule, tuning) pairs for a job's kernel family.
-std::vector<TuneEntry> tune_candidates(const rl_params* p, const Config& base) {
-    std::vector<TuneEntry> v;
-    auto add = [&](int sched, int strip, int seg, int lpw, int gi) {
-        TuneEntry e{};
-        e.schedule = p->schedule == RL_SCHED_AUTO ? sched : p->schedule;
-        e.t.strip = strip;
-        e.t.seg = seg;
-        e.t.lines_per_wg = lpw;
-        e.t.graph_iters = gi;
-        v.push_back(e);
-    };
-    const bool thin = p->thin.mode != RL_THIN_OFF;
-    if (base.kind == KIND_RESIDENT) {
-        for (int seg : {4, 8, 16})
-            for (int lpw : {1, 2, 4}) add(RL_SCHED_RESIDENT, 0, seg, lpw, 0);
-        return v;
-    }
-    const int gi = thin ? 0 : 16;
-    for (int strip : {4, 8, 16}) {
-        add(RL_SCHED_TWO_PASS, strip, 0, 0, 0);
-        if (gi) add(RL_SCHED_TWO_PASS, strip, 0, 0, gi);
-    }
-    if (base.kind == KIND_SLIDE) add(RL_SCHED_TWO_PASS, 32, 0, 0, gi);
-    if (!thin && p->schedule == RL_SCHED_AUTO) {
-        add(RL_SCHED_FUSED, 0, 0, 0, 0);
-        add(RL_SCHED_FUSED, 0, 0, 0, gi);
-    }
-    return v;
-}
-
-rl_params with_entry(const rl_params* p, const TuneEntry& e) {
-    rl_params q = *p;
-    q.tuning = e.t;
-    q.schedule = e.schedule;
-    return q;
-}
-
-}  // namespace
 
 rl_status rl_autotune_workspace_bytes(const rl_params* p, size_t* bytes) {
     std::string why;

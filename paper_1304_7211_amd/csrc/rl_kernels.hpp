@@ -118,7 +118,8 @@ struct PhaseArgs {
     const int64_t* tile_count;     // its length (device)
     int32_t thin_mode, hyst, reset_period, full;  // thinning (full is derived per launch)
     float tau;
-    int32_t pad0;
+    int32_t list_ok;               // thinned non-full steps: 1 = use the tile list, 0 = all
+                                   // tiles (frozen pixels are still skipped per pixel)
     int64_t* sched;                // active-count ring (thinning)
     int64_t* active_total;         // running sum of |A_k|
     int32_t* act_part;             // 2 banks x ACT_SLOTS partial active counts
@@ -147,7 +148,7 @@ __device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
     p.tiles_a = t->tiles_a; p.tiles_b = t->tiles_b;
     p.tile_list = t->tile_list; p.tile_count = t->tile_count;
     p.thin_mode = t->thin_mode; p.hyst = t->hyst; p.reset_period = t->reset_period;
-    p.full = t->full; p.tau = t->tau; p.pad0 = 0;
+    p.full = t->full; p.tau = t->tau; p.list_ok = t->list_ok;
     p.sched = t->sched; p.active_total = t->active_total; p.act_part = t->act_part; p.k = t->k;
     return p;
 }
@@ -217,19 +218,22 @@ __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int T
     bool use_list = false;
     if (p.cnt) {
         p.full = (p.k == 0 || (p.reset_period > 0 && p.k % p.reset_period == 0)) ? 1 : 0;
-        use_list = !p.full;
+        use_list = !p.full && p.list_ok;
         if (!PHASE_B && local == 0 && threadIdx.x < 64)
             thin_finalize_wave(p.act_part, p.sched, p.active_total, p.k - 1, p.k);
     } else {
         p.full = 1;
     }
-    const int n = use_list ? (int)*p.tile_count : p.tiles_a * p.tiles_b;
+    // list length and entries through the constant address space: scalar loads, written
+    // by the rebuild before this launch
+    typedef const __attribute__((address_space(4))) int64_t* ConstI64Ptr;
+    const int n = use_list ? (int)*(ConstI64Ptr)p.tile_count : p.tiles_a * p.tiles_b;
     // XCD-aware order (single-job launches): workgroups local < n form a permutation of the
     // n tiles (or list entries, which are ascending tile ids) with one contiguous range per
     // XCD; workgroups past n (thinned steps with a short list) have no tile
     if (local >= n) return false;
     const int slot = (L.n_jobs == 1) ? xcd_tile(local, n) : local;
-    const int t = use_list ? p.tile_list[slot] : slot;
+    const int t = use_list ? ((ConstIntPtr)p.tile_list)[slot] : slot;
     a0 = (t % p.tiles_a) * TA;
     b0 = (t / p.tiles_a) * TB;
     return true;
@@ -311,16 +315,15 @@ __device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, 
     return 1;
 }
 
-// Per-wave sum of an int and one atomic add (thinned mode active counts).
-// Each wavefront adds its count into one of ACT_SLOTS counters of bank k & 1 (spread, so
-// thousands of wavefronts do not serialise on one address); integer adds, so the total
-// does not depend on their order.
-__device__ __forceinline__ void add_active(const PhaseArgs& p, int n_active) {
+// One atomic add per wavefront of its active-pixel count (thinned mode), into one of
+// ACT_SLOTS counters of bank k & 1 (spread, so thousands of wavefronts do not serialise on
+// one address); integer adds, so the total does not depend on their order.  wave_total is
+// wavefront-uniform (summed from ballots).
+__device__ __forceinline__ void add_active(const PhaseArgs& p, int wave_total) {
     if (!p.cnt) return;
-    for (int off = 32; off > 0; off >>= 1) n_active += __shfl_xor(n_active, off);
-    if ((threadIdx.x & 63) == 0 && n_active) {
+    if ((threadIdx.x & 63) == 0 && wave_total) {
         const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave_id()) % ACT_SLOTS);
-        atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + slot], n_active);
+        atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + slot], wave_total);
     }
 }
 
@@ -410,14 +413,16 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
                                               const float (&out)[S],
                                               const EpiPlan<ORIENT, S, NW>& plan) {
     const int lane = threadIdx.x & 63, wv = wave_id();
-    int n_active = 0;
+    int n_active = 0;  // wavefront total, summed from ballots (phase B, thinned)
     if (ORIENT == ORIENT_COLS) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             int y, x;
             epi_pos<ORIENT, S, NW>(s, a0, b0, y, x);
+            int act = 0;
             if (x < p.W && y < p.H)
-                n_active += epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[s], out[s]);
+                act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[s], out[s]);
+            if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
         }
     } else {
         constexpr int TB = NW * S;
@@ -432,9 +437,10 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
             int row = e / TB, col = e % TB;
             int y, x;
             epi_pos<ORIENT, S, NW>(i, a0, b0, y, x);
+            int act = 0;
             if (y < p.H && x < p.W)
-                n_active += epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[i],
-                                               lds[row * SP + col]);
+                act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[i], lds[row * SP + col]);
+            if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
         }
     }
     if (PHASE_B) add_active(p, n_active);

@@ -113,7 +113,7 @@ def test_tau_zero_is_plain_bit_exact(orc, mode):
 
 def test_active_list_is_flatnonzero():
     h = synth.disc(4)
-    thin = dict(REL)
+    thin = dict(REL, keep_list=True)
     f = synth.observe(synth.latent_image(170, 203, 33), h, "poisson", 33)
     job = Job(to_dev(f), h, thin=thin)
     checked = 0
@@ -129,6 +129,23 @@ def test_active_list_is_flatnonzero():
             job.iterate(1)
     job.close()
     assert checked == 4  # rebuilds at k = 1, 11, 21, 31
+
+
+def test_pixel_list_only_when_kept():
+    """Without keep_list only the tile list is built: no exported pixel list, and the
+    iterates are bit-identical to a job that keeps it."""
+    h = synth.disc(4)
+    f = synth.observe(synth.latent_image(170, 203, 34), h, "poisson", 34)
+    a = Job(to_dev(f), h, thin=dict(REL, keep_list=True))
+    b = Job(to_dev(f), h, thin=dict(REL))
+    a.iterate(23)
+    b.iterate(23)
+    assert a.active_list() is not None
+    assert b.active_list() is None
+    sa, sb = a.get_state(), b.get_state()
+    assert torch.equal(sa["u"], sb["u"]) and torch.equal(sa["cnt"], sb["cnt"])
+    a.close()
+    b.close()
 
 
 def test_free_running_small_config3_analogue(orc):
