@@ -345,6 +345,24 @@ def report_thinned(args, dev):
     N = job["f"].size
     sched = np.array(res["thinned"]["sched"], dtype=np.float64) / N
     omitted = 1.0 - sched.mean()
+    # threshold sweep (as in Table 2): time, omitted fraction and PSNR against plain
+    sweep = []
+    for tau in (3e-4, 1e-3, 3e-3, 1e-2):
+        thin = dict(job["thin"], tau=tau)
+        j = Job(f, job["psf"], thin=thin)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        j.iterate(K)
+        u = j.result()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sc = np.array(j.thin_schedule(), dtype=np.float64) / N
+        sweep.append(dict(tau=tau, ms=round(dt * 1e3, 2),
+                          speedup=round(res["plain"]["t"] / dt, 3),
+                          omitted_fraction=round(float(1.0 - sc.mean()), 4),
+                          psnr_vs_plain_db=round(_psnr(u.cpu().numpy(), res["plain"]["u"]), 2)))
+        j.close()
+        log(f"report 3: tau {tau}: {sweep[-1]}")
     return {
         "report": "thinned RL, config 3",
         "workload": "2048x2048, disc r=16, Poisson peak 1000, 500 iterations, rel tau 1e-4, H=5, R=10, C=10",
@@ -360,6 +378,7 @@ def report_thinned(args, dev):
         "active_fraction_last_10": [round(float(x), 4) for x in sched[-10:]],
         "flux_plain": res["plain"]["st"].flux,
         "flux_thinned": res["thinned"]["st"].flux,
+        "tau_sweep": sweep,
     }
 
 

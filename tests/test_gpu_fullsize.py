@@ -60,3 +60,54 @@ def test_config2_full_length_properties():
         if np.array_equal(h, h[::-1, :]) and np.array_equal(h, h[:, ::-1]):
             fsum = float(j["f"].astype(np.float64).sum())
             assert abs(st.flux - fsum) <= 1e-5 * fsum, (j["name"], st.flux, fsum)
+
+
+def _decisions(a, b32, mode, tau):
+    a32 = a.astype(np.float32)
+    t = np.float32(tau) * b32 if mode == "rel" else np.float32(tau)
+    return np.abs((a32 - b32).astype(np.float32)) < t
+
+
+@pytest.mark.parametrize("k0", [11, 20])
+def test_config3_full_size_lockstep(orc, k0):
+    """One thinned iteration at configuration 3's full size (2048 x 2048, disc r=16) from
+    a seeded synthetic state (u, stale r, counters with frozen blocks and scattered
+    active pixels): GPU against the oracle's thinned step, k0 = 11 (list rebuild) and
+    k0 = 20 (full step)."""
+    job = synth.job_for_config(3)[0]
+    f, h, thin = job["f"], job["psf"], dict(job["thin"])
+    H, W = f.shape
+    rng = np.random.default_rng(303)
+    u32 = (f * (1.0 + 0.01 * rng.standard_normal(f.shape))).clip(1e-3).astype(np.float32)
+    r32 = (1.0 + 0.05 * rng.standard_normal(f.shape)).clip(0.5).astype(np.float32)
+    hyst = thin["hysteresis"]
+    blocks = rng.random((H // 32, W // 32)) < 0.6
+    frozen = np.kron(blocks, np.ones((32, 32), bool)) | (rng.random(f.shape) < 0.2)
+    cnt = np.where(frozen, rng.integers(hyst, 40, f.shape), rng.integers(0, hyst, f.shape))
+    cnt = cnt.astype(np.uint8)
+    full = k0 % thin["reset_period"] == 0
+    active = np.ones(f.shape, bool) if full else cnt < hyst
+    u = u32.astype(np.float64)
+    r = r32.astype(np.float64)
+    c = cnt.copy()
+    n_act = orc.thin_step(f, u, r, c, h, k0, thin)
+    assert n_act == int(active.sum())
+    g = Job(to_dev(f), h, thin=thin)
+    g.set_state(u=to_dev(u32), r=to_dev(r32), cnt=to_dev(cnt), k=k0)
+    g.iterate(1)
+    st = g.get_state()
+    sched = g.thin_schedule()
+    gu, gr, gc = (st["u"].cpu().numpy(), st["r"].cpu().numpy(), st["cnt"].cpu().numpy())
+    g.close()
+    assert rel_err(gu, u) <= RTOL
+    assert rel_err(gr[active], r[active]) <= RTOL
+    assert np.array_equal(gu[~active], u32[~active])
+    assert np.array_equal(gr[~active], r32[~active])
+    assert sched[-1] == n_act
+    # counters: bit-exact outside the band where float32 rounding may decide either way
+    d = [_decisions(u * s, u32, thin["mode"], thin["tau"]) for s in (1 - 4e-7, 1.0, 1 + 4e-7)]
+    amb = active & ~((d[0] == d[1]) & (d[1] == d[2]))
+    want = np.where(d[1], np.minimum(cnt.astype(int) + 1, 255), 0).astype(np.uint8)
+    want = np.where(active, want, cnt)
+    assert np.array_equal(gc[~amb], want[~amb])
+    print(f"k0={k0} active={n_act} ambiguous={int(amb.sum())}")
