@@ -25,7 +25,10 @@ configuration:
   5  serving: Poisson arrivals of requests drawn from a pool (sides 128..4096, mixed
      PSFs, 50..500 iterations, thinning on) at 70 % of the measured batched capacity:
      p50/p99 latency and throughput of the continuous-batching server against the plain
-     one-at-a-time method on the same GPU.
+     one-at-a-time method on the same GPU;
+  6  rectangle PSFs (5x7, 15x15, 31x31, 63x9) at 1024^2 and 2048^2, 100 iterations: the
+     separable BOX_RECT kernels against the per-row sliding runs, px-it/s, per-launch
+     kernel time and HBM fraction of the phase kernels.
 """
 import argparse
 import json
@@ -93,6 +96,8 @@ def algorithmic_flops_per_px(kind, info, phase_b):
     plus the ratio's division (phase A) or the update's multiplication (phase B)."""
     if kind == "slide":
         conv = 2.0 * info["n_spans"]
+    elif kind == "rect":
+        conv = 4.0  # separable 2-D box: add and subtract per pass
     elif kind == "resident":
         conv = 2.0
     else:
@@ -111,7 +116,7 @@ def main():
     ap.add_argument("--mode", choices=["batch", "sequential"], default="batch")
     ap.add_argument("--compare", action="store_true",
                     help="also time the other mode (reported as 'other_mode')")
-    ap.add_argument("--report", type=int, choices=[3, 4, 5], default=None)
+    ap.add_argument("--report", type=int, choices=[3, 4, 5, 6], default=None)
     ap.add_argument("--requests", type=int, default=48, help="--report 5: requests")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the "
@@ -150,7 +155,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.report:
-        line = {3: report_thinned, 4: report_batched, 5: report_serving}[args.report](args, dev)
+        line = {3: report_thinned, 4: report_batched, 5: report_serving,
+                6: report_rect}[args.report](args, dev)
         print(json.dumps(line), flush=True)
         return
     jobs = synth.job_for_config(2)
@@ -228,7 +234,8 @@ def main():
             step()
         torch.cuda.synchronize()
         A.rl_timing_enable(False)
-        names = ["resident_box", "slide_conv_ratio", "slide_corr_update", "span_conv_ratio",
+        names = ["resident_box", "rect_conv_ratio", "rect_corr_update", "slide_conv_ratio",
+                 "slide_corr_update", "span_conv_ratio",
                  "span_corr_update", "direct_conv_ratio", "direct_corr_update"]
         for nm in names:
             n, ms = A.rl_timing_read(nm)
@@ -577,6 +584,54 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command):
             json.dumps(dict(source_sha256=src_hash, scale=dict(fetch=sf, write=sw),
                             bytes_per_launch=per_launch), indent=1), "```"]
     return "\n".join(out)
+
+
+def report_rect(args, dev):
+    import torch
+
+    import synth
+    from paper_1304_7211_amd import _abi as A
+    from paper_1304_7211_amd.job import Job
+    K = 100
+    rows = []
+    for my, mx in ((5, 7), (15, 15), (31, 31), (63, 9)):
+        h = synth.box_rect(my, mx)
+        for side in (1024, 2048):
+            f = torch.from_numpy(synth.observe(synth.latent_image(side, side, 6), h,
+                                               "gaussian", 6)).to(dev)
+            row = dict(psf=f"{my}x{mx}", side=side)
+            for path in ("runs", "box_rect"):
+                j = Job(f, h, path=path)
+                j.iterate(3)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                j.iterate(K)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                A.rl_timing_reset()
+                A.rl_timing_enable(True)
+                j.iterate(10)
+                torch.cuda.synchronize()
+                A.rl_timing_enable(False)
+                kind = "rect" if path == "box_rect" else None
+                us = []
+                for nm in ("rect_conv_ratio", "rect_corr_update", "slide_conv_ratio",
+                           "slide_corr_update", "span_conv_ratio", "span_corr_update"):
+                    n, ms = A.rl_timing_read(nm)
+                    if n:
+                        us.append(1e3 * ms / n)
+                A.rl_timing_reset()
+                j.close()
+                avg = sum(us) / len(us)
+                row[path] = dict(px_it_per_s=side * side * K / dt, us_per_it=1e6 * dt / K,
+                                 kernel_us=round(avg, 2),
+                                 hbm_frac=round(BYTES_PER_PX_PHASE * side * side / (avg * 1e-6)
+                                                / (PEAK_HBM_GBS * 1e9), 4))
+            row["speedup"] = round(row["runs"]["us_per_it"] / row["box_rect"]["us_per_it"], 3)
+            rows.append(row)
+            log(f"report 6: {row}")
+    return {"report": "rectangle PSFs: separable BOX_RECT vs sliding runs",
+            "iterations": K, "rows": rows}
 
 
 def cpu_baseline(jobs):

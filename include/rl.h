@@ -62,6 +62,9 @@ typedef int32_t rl_status;
 #define RL_PATH_BOX_AXIS 2 /* 1 x L or L x 1 uniform box: sliding window (Section 3)       */
 #define RL_PATH_RUNS 3     /* per-row runs: sliding for uniform runs (generic box filter),
                               register-blocked spans for non-uniform rows (list filter)    */
+#define RL_PATH_BOX_RECT 4 /* kh x kw uniform rectangle (kh, kw >= 2): separable sliding
+                              sums, rows then columns, on an LDS tile (2-D box filter,
+                              Section 3); constant work per pixel in kh and kw            */
 
 /* iteration schedule: how the per-iteration kernels are organised */
 #define RL_SCHED_AUTO 0

@@ -84,8 +84,20 @@ bool compile_psf(const float* psf, int kh, int kw, CompiledPsf* out, std::string
             }
         }
     }
+    // rectangle: one run per row, consecutive rows, equal column span and weight bits
+    if (!c.is_axis_box && c.runs.size() >= 2) {
+        const Run& r0 = c.runs[0];
+        bool ok = r0.x1 > r0.x0;
+        for (size_t q = 1; ok && q < c.runs.size(); ++q) {
+            const Run& r = c.runs[q];
+            ok = r.dy == c.runs[q - 1].dy + 1 && r.x0 == r0.x0 && r.x1 == r0.x1 &&
+                 bits_of(r.w) == bits_of(r0.w);
+        }
+        c.is_rect = ok;
+    }
     if (c.n_taps == 1) c.auto_path = RL_PATH_DIRECT;  // bit-exact identity for a delta
     else if (c.is_axis_box) c.auto_path = RL_PATH_BOX_AXIS;
+    else if (c.is_rect) c.auto_path = RL_PATH_BOX_RECT;
     else c.auto_path = RL_PATH_RUNS;
     *out = std::move(c);
     return true;

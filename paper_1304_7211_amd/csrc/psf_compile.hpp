@@ -50,6 +50,9 @@ struct CompiledPsf {
     Orient box_orient = Orient::Rows;
     int32_t box_len = 0, box_c0 = 0;  // correlation-form offset of the first tap (conv)
     float box_w = 0.f;
+    // full uniform rectangle of at least 2 x 2 taps (every tap of a kh x kw block present
+    // and bit-identical); the block may sit anywhere in the PSF array
+    bool is_rect = false;
 };
 
 // Validates (finite, >= 0, positive sum) and compiles.  Returns false with a reason.

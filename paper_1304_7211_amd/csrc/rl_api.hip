@@ -36,7 +36,7 @@ constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3 };
+enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3, KIND_RECT = 4 };
 
 // ---- kernel timing registry -----------------------------------------------------------
 struct TimedLaunch {
@@ -178,9 +178,13 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     const int H = p->height, W = p->width;
     const bool thin = p->thin.mode != RL_THIN_OFF;
     int path = p->path == RL_PATH_AUTO ? c.auto_path : p->path;
-    if (path < RL_PATH_DIRECT || path > RL_PATH_RUNS) { *why = "unknown path"; return RL_E_INVAL; }
+    if (path < RL_PATH_DIRECT || path > RL_PATH_BOX_RECT) { *why = "unknown path"; return RL_E_INVAL; }
     if (path == RL_PATH_BOX_AXIS && !c.is_axis_box) {
         *why = "BOX_AXIS path needs a 1 x L or L x 1 uniform box PSF";
+        return RL_E_INVAL;
+    }
+    if (path == RL_PATH_BOX_RECT && !c.is_rect) {
+        *why = "BOX_RECT path needs a uniform rectangle of at least 2 x 2 taps";
         return RL_E_INVAL;
     }
     cfg->path = path;
@@ -283,6 +287,14 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         cfg->lmax = 1;
         cfg->conv = rl::build_tap_table(h, kh, kw, false);
         cfg->corr = rl::build_tap_table(h, kh, kw, true);
+    } else if (path == RL_PATH_BOX_RECT) {
+        if (slide_S != 4 && slide_S != 8) { *why = "BOX_RECT runs strips of 4 or 8"; return RL_E_UNSUPPORTED; }
+        cfg->kind = KIND_RECT;
+        cfg->orient = rlk::ORIENT_ROWS;
+        cfg->S = slide_S;
+        cfg->lmax = 0;
+        cfg->conv = rl::build_op_table(h, kh, kw, false, rl::Orient::Rows, true, 0);
+        cfg->corr = rl::build_op_table(h, kh, kw, true, rl::Orient::Rows, true, 0);
     } else if (path == RL_PATH_BOX_AXIS) {
         cfg->kind = KIND_SLIDE;
         cfg->orient = box_orient;
@@ -335,6 +347,11 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             size_t ny = cfg->orient == rlk::ORIENT_ROWS ? na : nb;
             size_t nx = cfg->orient == rlk::ORIENT_ROWS ? nb : na;
             b = std::max(b, (ny * (nx | 1) + rlk::slide_scratch_floats<kNW>()) * sizeof(float));
+        }
+        if (cfg->kind == KIND_RECT) {
+            // tile plus the horizontal window sums of every tile row
+            size_t ny = 64 + t.lane_max - t.lane_min, nx = cfg->TB + t.c_max - t.c_min;
+            b = (ny * (nx | 1) + ny * (size_t)(cfg->TB + 1)) * sizeof(float);
         }
         return b;
     };
@@ -599,6 +616,11 @@ int persist_capacity(PersistFn fn, size_t lds) {
 constexpr int kSpinLimit = 1 << 22;  // polls before a persistent launch gives up
 
 PhaseFn phase_fn(const Config& c, bool phase_b) {
+    if (c.kind == KIND_RECT) {
+        if (c.S == 4) return phase_b ? rlk::rect_kernel<4, kNW, true> : rlk::rect_kernel<4, kNW, false>;
+        if (c.S == 8) return phase_b ? rlk::rect_kernel<8, kNW, true> : rlk::rect_kernel<8, kNW, false>;
+        return nullptr;
+    }
     if (c.kind == KIND_SPAN) {
         if (c.orient == rlk::ORIENT_ROWS)
             return phase_b ? span_fn_s<rlk::ORIENT_ROWS, true>(c.S, c.lmax)
@@ -612,6 +634,7 @@ PhaseFn phase_fn(const Config& c, bool phase_b) {
 }
 
 const char* phase_name(const Config& c, bool phase_b) {
+    if (c.kind == KIND_RECT) return phase_b ? "rect_corr_update" : "rect_conv_ratio";
     if (c.kind == KIND_SPAN)
         return phase_b ? (c.lmax == 1 ? "direct_corr_update" : "span_corr_update")
                        : (c.lmax == 1 ? "direct_conv_ratio" : "span_conv_ratio");

@@ -678,6 +678,118 @@ __global__ __launch_bounds__(NW * 64) void slide_kernel(LaunchArgs L) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Rectangle kernel (2-D box filter, separable): the operator is w times the sum over a
+// kh x kw window, rows lane_min..lane_max and columns c_min..c_max relative to the output
+// (ORIENT_ROWS tables).  On the LDS tile (64 + kh - 1 rows by TB + kw - 1 columns) a
+// horizontal pass forms the kw-wide window sums of every tile row for the TB output
+// columns (segments of 8 by sliding: one add and one subtract per step), then a vertical
+// pass slides kh-tall sums of those down segments of 8 output rows.  Seeds are direct sums
+// over four partial accumulators; the slides are Kahan-compensated when kahan = 1.  Work
+// per output is constant in kh and kw apart from the seeds.
+// ---------------------------------------------------------------------------------------
+constexpr int RECT_SEG = 8;
+
+template <int NW>
+__host__ __device__ constexpr int rect_hs_pitch(int TB) { return TB + 1; }
+
+__device__ __forceinline__ void rl_add(float& s, float& c, float x, bool kahan) {
+    if (kahan) kahan_add(s, c, x);
+    else s += x;
+}
+
+template <int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
+    constexpr int TB = NW * S;
+    constexpr int NSEG_H = TB / RECT_SEG;       // horizontal segments per tile row
+    constexpr int NV = TB * (64 / RECT_SEG);    // vertical tasks (column, row segment)
+    static_assert(NV <= NW * 64, "one vertical task per thread");
+    const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
+    const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
+    float* hs = lds + ny * pitch;  // ny rows of TB horizontal sums (pitch TB + 1)
+    const int tid = threadIdx.x;
+    const bool kahan = p.kahan != 0;
+    // vertical task of this thread and its outputs' epilogue inputs (loaded up front)
+    const int vb = tid % TB, vr = tid / TB;
+    const bool has_v = tid < NV;
+    EpiIn in[RECT_SEG];
+    if (has_v) {
+#pragma unroll
+        for (int j = 0; j < RECT_SEG; ++j) {
+            const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
+            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+        }
+    }
+    load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
+    lds_dma_wait();
+    __syncthreads();
+    // horizontal pass
+    for (int task = tid; task < ny * NSEG_H; task += NW * 64) {
+        const int r = task / NSEG_H, c0 = (task % NSEG_H) * RECT_SEG;
+        const float* row = lds + r * pitch + c0;
+        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        int t = 0;
+        for (; t + 4 <= kw; t += 4) {
+            q0 += row[t];
+            q1 += row[t + 1];
+            q2 += row[t + 2];
+            q3 += row[t + 3];
+        }
+        for (; t < kw; ++t) q0 += row[t];
+        float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
+        float* out = hs + r * rect_hs_pitch<NW>(TB) + c0;
+        out[0] = sum;
+#pragma unroll
+        for (int j = 1; j < RECT_SEG; ++j) {
+            rl_add(sum, comp, row[j + kw - 1] - row[j - 1], kahan);
+            out[j] = sum - comp;
+        }
+    }
+    __syncthreads();
+    // vertical pass and epilogue
+    int n_active = 0;
+    const float w = as_const(p.spans)[0].w0;
+    float v[RECT_SEG];
+    if (has_v) {
+        const int hp = rect_hs_pitch<NW>(TB);
+        const float* col = hs + (vr * RECT_SEG) * hp + vb;
+        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        int i = 0;
+        for (; i + 4 <= kh; i += 4) {
+            q0 += col[i * hp];
+            q1 += col[(i + 1) * hp];
+            q2 += col[(i + 2) * hp];
+            q3 += col[(i + 3) * hp];
+        }
+        for (; i < kh; ++i) q0 += col[i * hp];
+        float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
+        v[0] = sum;
+#pragma unroll
+        for (int j = 1; j < RECT_SEG; ++j) {
+            rl_add(sum, comp, col[(j + kh - 1) * hp] - col[(j - 1) * hp], kahan);
+            v[j] = sum - comp;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RECT_SEG; ++j) {
+        int act = 0;
+        const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
+        if (has_v && y < p.H && x < p.W)
+            act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, in[j], w * v[j]);
+        if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+    }
+    if (PHASE_B) add_active(p, n_active);
+}
+
+template <int S, int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void rect_kernel(LaunchArgs L) {
+    extern __shared__ float lds[];
+    int a0, b0;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, 64, NW * S, a0, b0)) return;
+    rect_tile<S, NW, PHASE_B>(p, a0, b0, lds);
+}
+
+// ---------------------------------------------------------------------------------------
 // Persistent schedule (plain RL): one launch runs every phase of every iteration of one or
 // more jobs.  A task is (step s, tile t) with step s = 2 (k - k0) + phase; tasks are
 // numbered step by step (q = s * total_tiles + tile index) and handed out in that order by

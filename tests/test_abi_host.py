@@ -70,6 +70,19 @@ def test_auto_classification(A):
     assert A.rl_psf_runs(synth.disc(10))[2] == A.RL_PATH_RUNS
     assert A.rl_psf_runs(synth.oblique_line(31, 30.0))[2] == A.RL_PATH_RUNS
     assert A.rl_psf_runs(synth.dense_random(15, 1))[2] == A.RL_PATH_RUNS
+    assert A.rl_psf_runs(synth.box_rect(5, 7))[2] == A.RL_PATH_BOX_RECT
+    assert A.rl_psf_runs(synth.box_rect(2, 2))[2] == A.RL_PATH_BOX_RECT
+    # a rectangle with one different tap, or with a hole, is not a box
+    h = np.ones((4, 6), np.float32)
+    h[2, 3] = 2.0
+    assert A.rl_psf_runs(h)[2] == A.RL_PATH_RUNS
+    h = np.ones((4, 6), np.float32)
+    h[1, 0] = 0.0
+    assert A.rl_psf_runs(h)[2] == A.RL_PATH_RUNS
+    # a rectangle inside zero margins is still a rectangle
+    h = np.zeros((7, 9), np.float32)
+    h[1:4, 2:8] = 1.0
+    assert A.rl_psf_runs(h)[2] == A.RL_PATH_BOX_RECT
     # a vertical line with gaps is not a box
     h = np.zeros((5, 1), np.float32)
     h[[0, 1, 3, 4]] = 0.25

@@ -40,7 +40,11 @@ CASES = [
     ("oblique31", lambda: synth.oblique_line(31, 30.0), ["direct", "runs"]),
     ("oblique47_steep", lambda: synth.oblique_line(47, 75.0), ["runs"]),
     ("dense15", lambda: synth.dense_random(15, 2), ["direct", "runs"]),
-    ("rect5x7", lambda: synth.box_rect(5, 7), ["runs"]),
+    ("rect5x7", lambda: synth.box_rect(5, 7), ["runs", "box_rect"]),
+    ("rect4x6_even", lambda: synth.box_rect(4, 6), ["direct", "box_rect"]),
+    ("rect2x2", lambda: synth.box_rect(2, 2), ["box_rect"]),
+    ("rect31x17", lambda: synth.box_rect(31, 17), ["runs", "box_rect"]),
+    ("rect_margin", lambda: np.pad(synth.box_rect(3, 6), ((2, 0), (0, 3))), ["box_rect"]),
 ]
 
 
@@ -63,11 +67,13 @@ def test_paths_match_oracle(orc, name, mk, paths, bc):
 # ---- tiny images: folds deeper than the image --------------------------------------------
 @pytest.mark.parametrize("shape", [(1, 1), (1, 5), (3, 2), (5, 9)])
 def test_tiny_deep_folds(orc, shape):
-    for h in [synth.box_h(15), synth.box_v(9), synth.disc(4), synth.oblique_line(11, 30.0)]:
+    for h in [synth.box_h(15), synth.box_v(9), synth.disc(4), synth.oblique_line(11, 30.0),
+              synth.box_rect(5, 7)]:
         f = _obs(*shape, synth.delta(), 3)
         f = np.maximum(f, 0.05).astype(np.float32)
         ref = orc.rl(f, h, 4)
-        for path in ["direct", "runs"] + (["box_axis"] if min(h.shape) == 1 else []):
+        for path in (["direct", "runs"] + (["box_axis"] if min(h.shape) == 1 else [])
+                     + (["box_rect"] if min(h.shape) > 1 and h.min() > 0 else [])):
             u, _ = run_gpu(f, h, 4, path=path)
             assert rel_err(u, ref) <= RTOL, (shape, h.shape, path)
 
@@ -77,14 +83,16 @@ def test_integer_images_bit_exact(orc):
     rng = np.random.default_rng(4)
     f = rng.integers(1, 256, size=(70, 90)).astype(np.float32)
     for h01 in [np.ones((1, 9), np.float32), np.ones((7, 1), np.float32),
-                (synth.disc(3) > 0).astype(np.float32)]:
+                (synth.disc(3) > 0).astype(np.float32), np.ones((5, 7), np.float32)]:
         # one conv only: v = f*h with integer weights; with K=1 u^1 = u^0 * corr(f/v)
         # ratio and update round, so compare the forward convolution through a lock-step
         # property: for u0 = f and f' = f*h (exact integers), r = 1 exactly and
         # u^1 = f * sum(h) exactly.
         fb = orc.conv(f.astype(np.float64), h01).astype(np.float32)
         assert np.array_equal(fb.astype(np.float64), orc.conv(f.astype(np.float64), h01))
-        for path in ["direct", "runs"] + (["box_axis"] if min(h01.shape) == 1 else []):
+        rect = min(h01.shape) > 1 and h01.min() > 0
+        for path in (["direct", "runs"] + (["box_axis"] if min(h01.shape) == 1 else [])
+                     + (["box_rect"] if rect else [])):
             scheds = ["two_pass", "resident"] if path == "box_axis" else ["auto"]
             for sched in scheds:
                 u, _ = run_gpu(fb, h01, 1, path=path, schedule=sched, u0=to_dev(f))

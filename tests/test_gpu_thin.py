@@ -63,7 +63,16 @@ def _oracle_state(orc, f, h, thin, k0):
 @pytest.mark.parametrize("thin", [REL, PAPER], ids=["rel-H3", "paper-abs-H1"])
 @pytest.mark.parametrize("k0", [9, 10, 11, 13, 20])
 def test_lockstep_one_iteration(orc, thin, k0):
-    h = synth.disc(4)
+    _lockstep(orc, thin, k0, synth.disc(4))
+
+
+@pytest.mark.parametrize("k0", [10, 11, 13])
+def test_lockstep_rectangle(orc, k0):
+    """The separable rectangle kernel under thinning (tile list, per-pixel skipping)."""
+    _lockstep(orc, REL, k0, synth.box_rect(5, 7))
+
+
+def _lockstep(orc, thin, k0, h):
     f = synth.observe(synth.latent_image(150, 131, 31), h, "poisson", 31)
     u32, r32, cnt = _oracle_state(orc, f, h, thin, k0)
     # oracle side: one step from the float32 state
