@@ -30,6 +30,8 @@ def _mixed_jobs():
         ("hbox31_res", 64, 250, synth.box_h(31), {}, 13),
         ("disc5_thin", 140, 150, synth.disc(5), dict(thin=THIN), 25),
         ("obl15_thin", 120, 90, synth.oblique_line(15, 60.0), dict(thin=THIN), 16),
+        ("rect9x5", 170, 140, synth.box_rect(9, 5), {}, 10),
+        ("rect4x4_thin", 133, 97, synth.box_rect(4, 4), dict(thin=THIN), 15),
     ]
     out = []
     for i, (name, H, W, h, kw, K) in enumerate(spec):
