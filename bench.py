@@ -16,6 +16,8 @@ Prints ONE JSON line.  Options: --gpus (must be 1), --steps, --warmup, --no-cpu-
 
 --report N prints, instead of the benchmark line, one JSON report line for another
 configuration:
+  1  plain RL, 128x128, horizontal box 15, Poisson 255, 50 iterations: microseconds per
+     solve (init, iterations, result) for each path, and the error against the oracle;
   3  thinned RL, 2048x2048, disc r=16, Poisson 1000, 500 iterations, relative threshold
      1e-4 held 5 iterations, reset and recompaction every 10: thinning-rate schedule,
      omitted fraction, PSNR against the unthinned GPU run, both timings;
@@ -116,7 +118,7 @@ def main():
     ap.add_argument("--mode", choices=["batch", "sequential"], default="batch")
     ap.add_argument("--compare", action="store_true",
                     help="also time the other mode (reported as 'other_mode')")
-    ap.add_argument("--report", type=int, choices=[3, 4, 5, 6], default=None)
+    ap.add_argument("--report", type=int, choices=[1, 3, 4, 5, 6], default=None)
     ap.add_argument("--requests", type=int, default=48, help="--report 5: requests")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the "
@@ -155,8 +157,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.report:
-        line = {3: report_thinned, 4: report_batched, 5: report_serving,
-                6: report_rect}[args.report](args, dev)
+        line = {1: report_plain_small, 3: report_thinned, 4: report_batched,
+                5: report_serving, 6: report_rect}[args.report](args, dev)
         print(json.dumps(line), flush=True)
         return
     jobs = synth.job_for_config(2)
@@ -321,6 +323,38 @@ def main():
 def _psnr(a, b):
     mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def report_plain_small(args, dev):
+    import torch
+
+    import oracle
+    import synth
+    from paper_1304_7211_amd.job import Job
+    job = synth.job_for_config(1)[0]
+    f = torch.from_numpy(job["f"]).to(dev)
+    K = job["iters"]
+    ref = oracle.Oracle().rl(job["f"], job["psf"], K)
+    out = {}
+    for path, sched in (("auto", "auto"), ("box_axis", "two_pass"), ("runs", "auto"),
+                        ("direct", "auto")):
+        times = []
+        for rep in range(20):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            j = Job(f, job["psf"], path=path, schedule=sched)
+            j.iterate(K)
+            u = j.result()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            info = j.describe()
+            j.close()
+        err = float(np.max(np.abs(u.cpu().numpy() - ref) / np.maximum(np.abs(ref), 1e-4)))
+        out[f"{path}/{sched}"] = dict(us_per_solve=round(1e6 * float(np.median(times[5:])), 1),
+                                      schedule=info["schedule"], max_rel_err=err)
+        log(f"report 1: {path}/{sched}: {out[f'{path}/{sched}']}")
+    return {"report": "plain RL, config 1", "workload": "128x128, box 1x15, Poisson 255, 50 "
+            "iterations (median of 15 solves after 5 warm-ups, init to result)", "paths": out}
 
 
 def report_thinned(args, dev):

@@ -78,6 +78,12 @@ def _load(mutant=0):
         lib.oracle_below.restype = ctypes.c_int
         lib.oracle_below.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                      ctypes.c_float]
+        lib.oracle_tv_div.restype = None
+        lib.oracle_tv_div.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+        lib.oracle_rl_tv.restype = None
+        lib.oracle_rl_tv.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, dp, dp]
         lib.oracle_sum.restype = ctypes.c_double
         lib.oracle_sum.argtypes = [dp, ctypes.c_long]
         _libs[mutant] = lib
@@ -124,6 +130,28 @@ class Oracle:
         r = np.empty_like(f)
         self.lib.oracle_rl(fp, up, f.shape[0], f.shape[1], hp, h.shape[0], h.shape[1],
                            BC[bc], int(K), r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return u
+
+    def tv_div(self, u, eps):
+        """div(grad u / |grad u|_eps) of the TV-regularised variant (forward gradient,
+        backward divergence, zero flux at the edges)."""
+        u, up = self._d(u)
+        out = np.empty_like(u)
+        self.lib.oracle_tv_div(up, u.shape[0], u.shape[1], float(eps),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return out
+
+    def rl_tv(self, f, h, K, lam, eps, bc="reflect"):
+        """K iterations of TV-regularised RL from u^0 = f."""
+        f, fp = self._d(f)
+        u, up = self._d(np.array(f, dtype=np.float64, copy=True))
+        h, hp = self._d(h)
+        r = np.empty_like(f)
+        d = np.empty_like(f)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.lib.oracle_rl_tv(fp, up, f.shape[0], f.shape[1], hp, h.shape[0], h.shape[1],
+                              BC[bc], int(K), float(lam), float(eps), r.ctypes.data_as(dp),
+                              d.ctypes.data_as(dp))
         return u
 
     def below(self, a, b, mode, tau):

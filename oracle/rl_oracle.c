@@ -175,6 +175,66 @@ void oracle_rl(const double *f, double *u, int H, int W, const double *h, int kh
 }
 
 /*
+ * Regularised RL with a total-variation term (the variant of Dey et al., 2006; the paper
+ * names regularised RL among the methods its optimisations carry over to, Section 2):
+ *   u^{k+1} = u^k . c / (1 - lambda * div(grad u^k / |grad u^k|_eps)),  c as in eq. 3.
+ * Discretisation (a reading; the paper gives none): forward differences for the gradient,
+ *   gx(y,x) = u(y,x+1) - u(y,x),  gy(y,x) = u(y+1,x) - u(y,x),
+ * which are 0 across the last column / row (both boundary rules continue the image with
+ * its edge pixel there); n = (gx, gy) / sqrt(gx^2 + gy^2 + eps^2); backward differences for
+ * the divergence, div(y,x) = nx(y,x) - nx(y,x-1) + ny(y,x) - ny(y-1,x), with n = 0 before
+ * the first column / row.  Forward gradient and backward divergence are negative adjoints
+ * of each other, which the tests check.
+ */
+static double tv_n(const double *u, long H, long W, long y, long x, int axis)
+{
+    const double c = u[y * W + x];
+    const double gx = x + 1 < W ? u[y * W + x + 1] - c : 0.0;
+    const double gy = y + 1 < H ? u[(y + 1) * W + x] - c : 0.0;
+    return (axis == 0 ? gx : gy);
+}
+
+void oracle_tv_div(const double *u, int H, int W, double eps, double *div)
+{
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            double d = 0.0;
+            /* n at (y, x), (y, x-1) and (y-1, x) */
+            const long py[3] = {y, y, y - 1}, px[3] = {x, x - 1, x};
+            for (int q = 0; q < 3; ++q) {
+                if (py[q] < 0 || px[q] < 0) continue;
+                const double gx = tv_n(u, H, W, py[q], px[q], 0);
+                const double gy = tv_n(u, H, W, py[q], px[q], 1);
+                const double m = sqrt(gx * gx + gy * gy + eps * eps);
+                if (q == 0) d += gx / m + gy / m;
+                else if (q == 1) d -= gx / m;
+                else d -= gy / m;
+            }
+            div[y * W + x] = d;
+        }
+}
+
+/* K iterations of TV-regularised RL from u (in/out); r and div are work arrays. */
+void oracle_rl_tv(const double *f, double *u, int H, int W, const double *h, int kh, int kw,
+                  int bc, int K, double lambda, double eps, double *r, double *div)
+{
+    for (int k = 0; k < K; ++k) {
+        oracle_tv_div(u, H, W, eps, div);
+#pragma omp parallel for schedule(static)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x)
+                r[y * W + x] = ratio(f[y * W + x], conv_at(u, H, W, h, kh, kw, bc, y, x));
+#pragma omp parallel for schedule(static)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x) {
+                const double c = corr_at(r, H, W, h, kh, kw, bc, y, x);
+                u[y * W + x] = update(u[y * W + x], c) / (1.0 - lambda * div[y * W + x]);
+            }
+    }
+}
+
+/*
  * The convergence test of thinned RL, taken in single precision on the float32 values of
  * u^{k+1} (a) and u^k (b) (Section 4: "absolute changes ... below a given threshold").
  * ABS: |a-b| < tau;  REL: |a-b| < tau*b.  tau <= 0 never freezes; a pixel that stays 0

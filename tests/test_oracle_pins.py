@@ -321,3 +321,69 @@ def test_planted_mistakes_are_caught():
     assert _pins_pass(oracle.Oracle(0))
     for m in range(1, 8):
         assert not _pins_pass(oracle.Oracle(m)), f"mutant {m} passed the pins"
+
+
+# ---- TV-regularised variant (Dey et al. 2006; named as carrying over in Section 2) --------
+def test_tv_zero_lambda_is_plain_rl(orc):
+    h = synth.disc(3)
+    f = synth.observe(synth.latent_image(40, 33, 8), h, "poisson", 8)
+    assert np.array_equal(orc.rl_tv(f, h, 6, 0.0, 1e-3), orc.rl(f, h, 6))
+
+
+def test_tv_div_closed_forms(orc):
+    eps = 1e-3
+    # constant image: no gradient anywhere
+    assert np.array_equal(orc.tv_div(np.full((6, 7), 0.3), eps), np.zeros((6, 7)))
+    # ramp along x with slope a: the flux a/m leaves the first column and enters the last
+    H, W, a = 5, 9, 0.2
+    u = np.tile(a * np.arange(W, dtype=np.float64), (H, 1))
+    m = np.sqrt(a * a + eps * eps)
+    want = np.zeros((H, W))
+    want[:, 0] = a / m
+    want[:, -1] = -a / m
+    assert np.allclose(orc.tv_div(u, eps), want, rtol=0, atol=1e-15)
+    # single spike in a flat image: hand-derived values at the spike and its neighbours
+    u = np.zeros((7, 8))
+    u[3, 4] = 1.0
+    d = orc.tv_div(u, eps)
+    s1, s2 = np.sqrt(1 + eps * eps), np.sqrt(2 + eps * eps)
+    # n = (-1/s2, -1/s2) at the spike, (1/s1, 0) left of it, (0, 1/s1) above it, else 0
+    assert abs(d[3, 4] - (-2 / s2 - 2 / s1)) < 1e-14
+    assert abs(d[3, 3] - 1 / s1) < 1e-14                 # left neighbour: its own nx
+    assert abs(d[2, 4] - 1 / s1) < 1e-14                 # upper neighbour: its own ny
+    assert abs(d[3, 5] - 1 / s2) < 1e-14                 # right: minus the spike's nx
+    assert abs(d[4, 4] - 1 / s2) < 1e-14                 # lower: minus the spike's ny
+    others = np.ones(d.shape, bool)
+    others[3, 3:6] = False
+    others[2, 4] = others[4, 4] = False
+    assert np.abs(d[others]).max() < 1e-15
+    assert abs(d.sum()) < 1e-14                          # zero flux: the sum telescopes
+
+
+def test_tv_summation_by_parts(orc):
+    """Backward divergence is the negative adjoint of the forward gradient with zero flux at
+    the edges: sum div(n) v = -sum n . grad v, for n = grad u / |grad u|_eps."""
+    rng = np.random.default_rng(5)
+    u = rng.random((13, 11))
+    v = rng.random((13, 11))
+    eps = 0.05
+    div = orc.tv_div(u, eps)
+    gx = np.zeros_like(u)
+    gy = np.zeros_like(u)
+    gx[:, :-1] = np.diff(u, axis=1)
+    gy[:-1, :] = np.diff(u, axis=0)
+    m = np.sqrt(gx ** 2 + gy ** 2 + eps ** 2)
+    vx = np.zeros_like(v)
+    vy = np.zeros_like(v)
+    vx[:, :-1] = np.diff(v, axis=1)
+    vy[:-1, :] = np.diff(v, axis=0)
+    lhs = float((div * v).sum())
+    rhs = -float(((gx / m) * vx + (gy / m) * vy).sum())
+    assert abs(lhs - rhs) < 1e-12
+
+
+def test_tv_constant_fixed_point(orc):
+    h = synth.disc(4)
+    f = np.full((30, 26), 0.4)
+    u = orc.rl_tv(f, h, 5, 0.1, 1e-3)
+    assert np.allclose(u, f, rtol=0, atol=1e-15)
