@@ -120,6 +120,16 @@ typedef struct rl_params {
     rl_thin thin;           /* thinning; mode RL_THIN_OFF disables it                     */
     void *stream;           /* hipStream_t for every device operation of the job          */
     rl_tuning tuning;       /* kernel-shape knobs, zero-initialise for defaults           */
+    /* Total-variation regularisation (the regularised RL the paper names as carrying its
+     * optimisations over, Section 2; the variant of Dey et al.): the update becomes
+     * u^{k+1} = u^k . c / (1 - tv_lambda * div(grad u^k / sqrt(|grad u^k|^2 + tv_eps^2)))
+     * with a forward-difference gradient (0 across the last column / row) and a
+     * backward-difference divergence (no flux before the first column / row).
+     * tv_lambda = 0 disables it; else 0 < tv_lambda < 0.25 (keeps the denominator > 0)
+     * and tv_eps > 0.  Not combined with thinning, the resident or the fused schedule
+     * (RL_E_UNSUPPORTED).                                                                */
+    float tv_lambda;
+    float tv_eps;
 } rl_params;
 
 typedef struct rl_stats {

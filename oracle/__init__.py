@@ -141,10 +141,10 @@ class Oracle:
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return out
 
-    def rl_tv(self, f, h, K, lam, eps, bc="reflect"):
-        """K iterations of TV-regularised RL from u^0 = f."""
+    def rl_tv(self, f, h, K, lam, eps, bc="reflect", u0=None):
+        """K iterations of TV-regularised RL from u^0 = f (or ``u0``)."""
         f, fp = self._d(f)
-        u, up = self._d(np.array(f, dtype=np.float64, copy=True))
+        u, up = self._d(np.array(f if u0 is None else u0, dtype=np.float64, copy=True))
         h, hp = self._d(h)
         r = np.empty_like(f)
         d = np.empty_like(f)

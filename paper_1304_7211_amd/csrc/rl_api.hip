@@ -59,7 +59,8 @@ struct Config {
 
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
-        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, total;
+        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, tvg,
+        total;
 };
 
 // counters block (int64 slots)
@@ -190,6 +191,11 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     cfg->path = path;
     int sched = p->schedule;
     if (sched < RL_SCHED_AUTO || sched > RL_SCHED_PERSISTENT) { *why = "unknown schedule"; return RL_E_INVAL; }
+    const bool tv = p->tv_lambda > 0.f;
+    if (tv && (thin || sched == RL_SCHED_FUSED || sched == RL_SCHED_RESIDENT)) {
+        *why = "TV regularisation runs on the two-pass schedule without thinning";
+        return RL_E_UNSUPPORTED;
+    }
     if (sched == RL_SCHED_PERSISTENT) {
         // Switched off: its first GPU run did not finish, and no cause has been shown yet.
         *why = "the persistent schedule is switched off";
@@ -224,7 +230,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         return RL_OK;
     }
     const int box_orient = c.box_orient == rl::Orient::Rows ? rlk::ORIENT_ROWS : rlk::ORIENT_COLS;
-    if (path == RL_PATH_BOX_AXIS && !thin && (sched == RL_SCHED_AUTO || sched == RL_SCHED_RESIDENT)) {
+    if (path == RL_PATH_BOX_AXIS && !thin && !tv && (sched == RL_SCHED_AUTO || sched == RL_SCHED_RESIDENT)) {
         int n = box_orient == rlk::ORIENT_ROWS ? W : H;
         int m = box_orient == rlk::ORIENT_ROWS ? H : W;
         // the on-chip halo holds a single reflection: needs L - 1 <= line length
@@ -426,6 +432,7 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     L.red_i = take(rlk::RED_BLOCKS * 8);
     L.done = cfg.sched == RL_SCHED_PERSISTENT ? take(ntiles * 4) : 0;
     L.pctl = take(2 * sizeof(int32_t));  // persistent launches: ticket, abort flag
+    L.tvg = p->tv_lambda > 0.f ? take(N * 4) : 0;
     L.total = o;
     return L;
 }
@@ -435,6 +442,8 @@ rl_status validate_params(const rl_params* p, std::string* why) {
     if (p->height < 1 || p->width < 1) { *why = "image size must be >= 1"; return RL_E_INVAL; }
     if ((int64_t)p->height * p->width > (int64_t)1 << 30) { *why = "image too large"; return RL_E_INVAL; }
     if (p->boundary != RL_BC_REFLECT && p->boundary != RL_BC_REPLICATE) { *why = "boundary"; return RL_E_INVAL; }
+    if (!(p->tv_lambda >= 0.f && p->tv_lambda < 0.25f)) { *why = "tv_lambda in [0, 0.25)"; return RL_E_INVAL; }
+    if (p->tv_lambda > 0.f && !(p->tv_eps > 0.f && p->tv_eps < 1e30f)) { *why = "tv_eps > 0"; return RL_E_INVAL; }
     if (p->thin.mode < RL_THIN_OFF || p->thin.mode > RL_THIN_REL) { *why = "thin mode"; return RL_E_INVAL; }
     if (p->thin.mode != RL_THIN_OFF) {
         if (!(p->thin.tau >= 0.f) || std::isinf(p->thin.tau)) { *why = "tau"; return RL_E_INVAL; }
@@ -682,6 +691,7 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     a.k = k0;
     a.full = 1;
     a.list_ok = 1;
+    a.tvg = (phase_b && j->p.tv_lambda > 0.f) ? j->at<float>(j->L.tvg) : nullptr;
     if (j->p.thin.mode != RL_THIN_OFF) {
         a.cnt = j->at<uint8_t>(j->L.cnt);
         a.thin_mode = j->p.thin.mode;
@@ -748,6 +758,16 @@ bool use_tile_list(rl_job* j) {
     }
     const int64_t ntiles = (int64_t)j->cfg.tiles_a * j->cfg.tiles_b;
     return j->tc_known < 0 || j->tc_known * 10 < ntiles * 9;
+}
+
+// TV-regularised jobs: the update's denominator from u^k, before phase A of an iteration
+// (phase B overwrites u^k).
+rl_status enqueue_tv(rl_job* j, hipStream_t s) {
+    if (!(j->p.tv_lambda > 0.f)) return RL_OK;
+    return dev_err(launch("tv_factor", rlk::tv_factor_kernel, dim3(grid_for(j->N, 256, 4096)),
+                          dim3(256), 0, s, (const float*)j->at<float>(j->L.u),
+                          j->at<float>(j->L.tvg), j->H, j->W, j->p.tv_lambda, j->p.tv_eps),
+                   "tv_factor");
 }
 
 rl_status enqueue_iterations(rl_job* j, int32_t n);
@@ -929,6 +949,7 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
         }
         la.kb = lb.kb = j->k;
         if (thin) la.one.list_ok = lb.one.list_ok = use_tile_list(j) ? 1 : 0;
+        if (rl_status tst = enqueue_tv(j, s)) return tst;
         rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, la), na);
         if (st) return st;
         st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lb), nbn);
@@ -1377,6 +1398,8 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
             }
             int m = 0;
             while (m < (int)g.idx.size() && n_iter[g.idx[m]] > kb) ++m;
+            for (int q = 0; q < m; ++q)
+                if ((st = enqueue_tv(jobs[g.idx[q]], gsm))) return st;
             for (int phase = 0; phase < 2; ++phase) {
                 rlk::LaunchArgs la{};
                 la.table = reinterpret_cast<const PhaseArgs*>(base + (phase ? g.off_b : g.off_a));

@@ -124,6 +124,7 @@ struct PhaseArgs {
     int64_t* active_total;         // running sum of |A_k|
     int32_t* act_part;             // 2 banks x ACT_SLOTS partial active counts
     int64_t k;                     // base iteration index (plus LaunchArgs::kb)
+    const float* tvg;              // phase B: TV denominator 1 - lambda div(...) or NULL
 };
 
 // One launch covers the tiles of n_jobs jobs: job j owns workgroups
@@ -150,6 +151,7 @@ __device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
     p.thin_mode = t->thin_mode; p.hyst = t->hyst; p.reset_period = t->reset_period;
     p.full = t->full; p.tau = t->tau; p.list_ok = t->list_ok;
     p.sched = t->sched; p.active_total = t->active_total; p.act_part = t->act_part; p.k = t->k;
+    p.tvg = t->tvg;
     return p;
 }
 
@@ -285,6 +287,7 @@ __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0); 
 // is applied, so the global loads overlap.
 struct EpiIn {
     float x;
+    float g;  // phase B with TV regularisation: the denominator of the update
     uint8_t c8;
 };
 
@@ -292,6 +295,7 @@ template <bool PHASE_B>
 __device__ __forceinline__ EpiIn epi_load(const PhaseArgs& p, size_t q) {
     EpiIn e;
     e.x = PHASE_B ? p.u[q] : p.f[q];
+    e.g = (PHASE_B && p.tvg) ? p.tvg[q] : 1.f;
     e.c8 = p.cnt ? p.cnt[q] : (uint8_t)0;
     return e;
 }
@@ -306,6 +310,7 @@ __device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, 
         p.r[q] = rl_ratio(e.x, val);
     } else {
         float un = __fmul_rn(e.x, val);
+        if (p.tvg) un = __fdiv_rn(un, e.g);
         p.u[q] = un;
         if (p.cnt && p.thin_mode != THIN_OFF) {
             bool below = thin_below(un, e.x, p.thin_mode, p.tau);
@@ -1437,6 +1442,45 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const double* partial
 }
 
 // f must be finite and >= 0; sets *flag = 1 otherwise.
+// Denominator of the TV-regularised update, g = 1 - lambda * div(grad u / |grad u|_eps):
+// forward-difference gradient (0 across the last column / row), backward-difference
+// divergence (no flux before the first column / row).  One thread per pixel, reading the
+// pixel, its right and lower neighbours and the two pixels that feed n at (y, x-1) and
+// (y-1, x).
+__device__ __forceinline__ void tv_n_at(const float* u, int H, int W, int y, int x, float eps2,
+                                        float& nx, float& ny) {
+    const float c = u[(size_t)y * W + x];
+    const float gx = x + 1 < W ? u[(size_t)y * W + x + 1] - c : 0.f;
+    const float gy = y + 1 < H ? u[(size_t)(y + 1) * W + x] - c : 0.f;
+    const float m = __fsqrt_rn(gx * gx + gy * gy + eps2);
+    nx = __fdiv_rn(gx, m);
+    ny = __fdiv_rn(gy, m);
+}
+
+__global__ __launch_bounds__(256) void tv_factor_kernel(const float* u, float* g, int H, int W,
+                                                        float lambda, float eps) {
+    const int64_t N = (int64_t)H * W;
+    const float eps2 = eps * eps;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < N;
+         q += (int64_t)gridDim.x * 256) {
+        const int y = (int)(q / W), x = (int)(q - (int64_t)y * W);
+        float nx, ny, d;
+        tv_n_at(u, H, W, y, x, eps2, nx, ny);
+        d = nx + ny;
+        if (x > 0) {
+            float ax, ay;
+            tv_n_at(u, H, W, y, x - 1, eps2, ax, ay);
+            d -= ax;
+        }
+        if (y > 0) {
+            float bx, by;
+            tv_n_at(u, H, W, y - 1, x, eps2, bx, by);
+            d -= by;
+        }
+        g[q] = 1.f - lambda * d;
+    }
+}
+
 __global__ __launch_bounds__(256) void check_f_kernel(const float* f, int64_t N, int32_t* flag) {
     int bad = 0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N;

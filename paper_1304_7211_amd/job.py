@@ -15,7 +15,7 @@ def _stream_ptr(stream):
 
 
 def make_params(f, psf, boundary="reflect", path="auto", schedule="auto", kahan=True,
-                thin=None, u0=None, stream=None, tuning=None):
+                thin=None, u0=None, stream=None, tuning=None, tv=None):
     """Build an rl_params for a float32 CUDA image f (H, W) and a float32 numpy PSF."""
     if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float32
             and f.dim() == 2 and f.is_contiguous()):
@@ -44,6 +44,9 @@ def make_params(f, psf, boundary="reflect", path="auto", schedule="auto", kahan=
         p.tuning.seg = int(tuning.get("seg", 0))
         p.tuning.lines_per_wg = int(tuning.get("lines_per_wg", 0))
         p.tuning.graph_iters = int(tuning.get("graph_iters", 0))
+    if tv:
+        p.tv_lambda = float(tv["lam"])
+        p.tv_eps = float(tv.get("eps", 1e-3))
     return p, psf  # keep psf alive until rl_init has copied it
 
 
@@ -75,8 +78,9 @@ def tune_lookup(f, psf, **kw):
 
 class Job:
     def __init__(self, f, psf, boundary="reflect", path="auto", schedule="auto", kahan=True,
-                 thin=None, u0=None, stream=None, workspace=None, tuning=None):
-        p, keep = make_params(f, psf, boundary, path, schedule, kahan, thin, u0, stream, tuning)
+                 thin=None, u0=None, stream=None, workspace=None, tuning=None, tv=None):
+        p, keep = make_params(f, psf, boundary, path, schedule, kahan, thin, u0, stream, tuning,
+                              tv)
         self.nbytes = A.rl_workspace_bytes(p)
         if workspace is None:
             workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=f.device)

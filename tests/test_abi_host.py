@@ -141,6 +141,17 @@ def test_workspace_bytes_and_validation(A):
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
     p, k9 = _params(A, psf=synth.box_h(9), schedule=A.RL_SCHED_RESIDENT)
     assert _ws_status(A, p)[0] == A.RL_OK
+    # TV regularisation: lambda in [0, 0.25), eps > 0, not with thinning
+    p, k12 = _params(A)
+    p.tv_lambda, p.tv_eps = 0.1, 1e-3
+    assert _ws_status(A, p)[0] == A.RL_OK
+    p.tv_lambda = 0.25
+    assert _ws_status(A, p)[0] == A.RL_E_INVAL
+    p.tv_lambda, p.tv_eps = 0.1, 0.0
+    assert _ws_status(A, p)[0] == A.RL_E_INVAL
+    p, k13 = _params(A, thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
+    p.tv_lambda, p.tv_eps = 0.1, 1e-3
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
     # the persistent schedule is switched off
     p, k10 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT)
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED

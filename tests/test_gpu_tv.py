@@ -1,0 +1,111 @@
+"""TV-regularised RL on the GPU against the FP64 oracle (rl_tv), through every tiled path,
+both boundaries, ragged sizes; batched and graph-replayed runs bit-identical to plain
+per-job runs.
+
+The TV factor's sensitivity to u grows like lambda / eps (the normalised gradient turns
+sharply where |grad u| ~ eps), so float32 rounding already present in u^k is amplified
+from iteration to iteration: free-running runs are compared at lambda / eps = 0.2
+(lambda = 4e-3, eps = 2e-2, about 5 grey levels of an 8-bit image on [0, 1]); at
+lambda / eps = 1 the error after 8 iterations reaches ~1.3e-5.  Strong regularisation
+(lambda = 0.2, eps = 1e-3) is checked lock-step -- one iteration from the oracle's float32
+state -- where no earlier rounding is amplified (errors ~4e-7)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import RTOL, rel_err, run_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1304_7211_amd._abi import RLError  # noqa: E402
+from paper_1304_7211_amd.job import BatchRunner, Job  # noqa: E402
+
+EPS, LAM = 2e-2, 4e-3
+
+CASES = [("disc6", lambda: synth.disc(6), ["runs", "direct"]),
+         ("oblique21", lambda: synth.oblique_line(21, 40.0), ["runs"]),
+         ("box_h15", lambda: synth.box_h(15), ["box_axis"]),
+         ("rect5x7", lambda: synth.box_rect(5, 7), ["box_rect"]),
+         ("dense9", lambda: synth.dense_random(9, 3), ["direct", "runs"])]
+
+
+def _obs(H, W, h, seed):
+    return synth.observe(synth.latent_image(H, W, seed), h, "poisson", seed)
+
+
+@pytest.mark.parametrize("name,mk,paths", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("bc", ["reflect", "replicate"])
+def test_tv_matches_oracle(orc, name, mk, paths, bc):
+    h = mk()
+    f = _obs(147, 203, h, 61)
+    # 8 free-running iterations at moderate regularisation
+    ref = orc.rl_tv(f, h, 8, LAM, EPS, bc)
+    for path in paths:
+        u, info = run_gpu(f, h, 8, boundary=bc, path=path, tv=dict(lam=LAM, eps=EPS))
+        err = rel_err(u, ref)
+        print(f"{name} {bc} {path} K=8: {err:.3g}")
+        assert err <= RTOL, (name, path, err)
+    # strong regularisation, lock-step: one iteration from the oracle's float32 state
+    # after 3 iterations, so no amplification of earlier rounding enters
+    u3 = orc.rl_tv(f, h, 3, 0.2, 1e-3, bc).astype(np.float32)
+    ref1 = orc.rl_tv(f, h, 1, 0.2, 1e-3, bc, u0=u3)
+    for path in paths:
+        u1, _ = run_gpu(f, h, 1, boundary=bc, path=path, u0=to_dev(u3),
+                        tv=dict(lam=0.2, eps=1e-3))
+        err = rel_err(u1, ref1)
+        print(f"{name} {bc} {path} lock-step lambda 0.2: {err:.3g}")
+        assert err <= RTOL, (name, path, err)
+    # the regularisation changes the result
+    plain, _ = run_gpu(f, h, 8, boundary=bc, path=paths[0])
+    assert not np.array_equal(plain, u)
+
+
+def test_tv_tiny_images(orc):
+    h = synth.disc(3)
+    for shape in [(1, 1), (1, 6), (5, 1), (3, 4)]:
+        f = np.maximum(_obs(*shape, synth.delta(), 4), 0.05).astype(np.float32)
+        ref = orc.rl_tv(f, h, 5, 0.1, 1e-2)
+        u, _ = run_gpu(f, h, 5, tv=dict(lam=0.1, eps=1e-2))
+        assert rel_err(u, ref) <= RTOL, shape
+
+
+def test_tv_batch_and_graph_bit_identical():
+    specs = [(synth.disc(5), 120, 150, 9), (synth.box_rect(4, 6), 90, 200, 12),
+             (synth.oblique_line(17, 60.0), 160, 100, 7)]
+    tv = dict(lam=0.05, eps=EPS)
+    fs = [_obs(H, W, h, 70 + i) for i, (h, H, W, K) in enumerate(specs)]
+    alone = []
+    for (h, H, W, K), f in zip(specs, fs):
+        j = Job(to_dev(f), h, tv=tv)
+        j.iterate(K)
+        alone.append(j.result().cpu().numpy())
+        j.close()
+    jobs = [Job(to_dev(f), h, tv=tv) for (h, H, W, K), f in zip(specs, fs)]
+    BatchRunner(len(jobs)).iterate(jobs, [K for (*_, K) in specs])
+    for j, a in zip(jobs, alone):
+        assert np.array_equal(j.result().cpu().numpy(), a)
+        j.close()
+    h, H, W, K = specs[0]
+    g = Job(to_dev(fs[0]), h, tv=tv, tuning=dict(graph_iters=4))
+    g.iterate(K)
+    assert np.array_equal(g.result().cpu().numpy(), alone[0])
+    g.close()
+
+
+def test_tv_rejected_combinations():
+    h = synth.box_h(9)
+    f = to_dev(_obs(64, 80, h, 2))
+    with pytest.raises(RLError):
+        Job(f, h, tv=dict(lam=0.05), thin=dict(mode="rel", tau=1e-3))
+    with pytest.raises(RLError):
+        Job(f, h, tv=dict(lam=0.05), schedule="resident")
+    with pytest.raises(RLError):
+        Job(f, h, tv=dict(lam=0.3))
+    # AUTO on an axis box with TV takes the two-pass schedule
+    j = Job(f, h, tv=dict(lam=0.05))
+    assert j.describe()["schedule"] == 1
+    j.close()
