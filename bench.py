@@ -236,7 +236,8 @@ def main():
             step()
         torch.cuda.synchronize()
         A.rl_timing_enable(False)
-        names = ["resident_box", "rect_conv_ratio", "rect_corr_update", "slide_conv_ratio",
+        names = ["resident_box", "mixed_conv_ratio", "mixed_corr_update", "rect_conv_ratio",
+                 "rect_corr_update", "slide_conv_ratio",
                  "slide_corr_update", "span_conv_ratio",
                  "span_corr_update", "direct_conv_ratio", "direct_corr_update"]
         for nm in names:
@@ -248,25 +249,24 @@ def main():
             dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
             kinfo = kernels[dom]
             kind = dom.split("_")[0]
-            # which job ran the dominant kernel
-            jname = None
-            for j in jobs:
-                inf = infos[j["name"]]
-                if kind == "resident" and inf["schedule"] == A.RL_SCHED_RESIDENT:
-                    jname = j["name"]
-                elif kind == "slide" and inf["schedule"] != A.RL_SCHED_RESIDENT and inf["lmax"] == 0:
-                    jname = j["name"]
-                elif kind in ("span", "direct") and inf["lmax"] > 0:
-                    jname = j["name"]
-            inf = infos[jname]
-            jj = [j for j in jobs if j["name"] == jname][0]
-            npx = jj["f"].size
-            if kind == "resident":
-                units = npx * jj["iters"]
-            else:
-                units = npx
-            fl = algorithmic_flops_per_px(kind, inf, dom.endswith("update")) * units
-            by = BYTES_PER_PX_PHASE * npx
+            # the jobs the dominant kernel ran (a mixed launch covers span and sliding jobs)
+            def job_kind(inf):
+                if inf["schedule"] == A.RL_SCHED_RESIDENT:
+                    return "resident"
+                if inf["path"] == A.RL_PATH_BOX_RECT:
+                    return "rect"
+                return "slide" if inf["lmax"] == 0 else ("direct" if inf["lmax"] == 1 else "span")
+            covered = [j for j in jobs
+                       if (job_kind(infos[j["name"]]) == kind
+                           or (kind == "mixed" and job_kind(infos[j["name"]]) in ("span", "slide", "direct")))]
+            jname = "+".join(j["name"] for j in covered)
+            fl = by = 0.0
+            for jj in covered:
+                inf = infos[jj["name"]]
+                npx = jj["f"].size
+                units = npx * jj["iters"] if kind == "resident" else npx
+                fl += algorithmic_flops_per_px(job_kind(inf), inf, dom.endswith("update")) * units
+                by += BYTES_PER_PX_PHASE * npx
             # roofline: the bound is the resource whose peak gives the longer minimum time
             t_alu = fl / (PEAK_FP32_TFLOPS * 1e12)
             t_hbm = by / (PEAK_HBM_GBS * 1e9)
@@ -552,7 +552,7 @@ def report_serving(args, dev):
 def _timing_name(kernel):
     """Map a rocprofv3 kernel symbol to the library's timing-registry name."""
     import re
-    m = re.search(r"rlk::(slide|span|resident)_kernel<([^>]*)>", kernel)
+    m = re.search(r"rlk::(slide|span|resident|rect|mixed)_kernel<([^>]*)>", kernel)
     if not m:
         return None
     kind, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]

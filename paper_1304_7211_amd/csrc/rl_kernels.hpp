@@ -287,7 +287,6 @@ __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0); 
 // is applied, so the global loads overlap.
 struct EpiIn {
     float x;
-    float g;  // phase B with TV regularisation: the denominator of the update
     uint8_t c8;
 };
 
@@ -295,7 +294,6 @@ template <bool PHASE_B>
 __device__ __forceinline__ EpiIn epi_load(const PhaseArgs& p, size_t q) {
     EpiIn e;
     e.x = PHASE_B ? p.u[q] : p.f[q];
-    e.g = (PHASE_B && p.tvg) ? p.tvg[q] : 1.f;
     e.c8 = p.cnt ? p.cnt[q] : (uint8_t)0;
     return e;
 }
@@ -310,7 +308,9 @@ __device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, 
         p.r[q] = rl_ratio(e.x, val);
     } else {
         float un = __fmul_rn(e.x, val);
-        if (p.tvg) un = __fdiv_rn(un, e.g);
+        // TV-regularised jobs: the denominator is read here rather than prefetched, so
+        // plain jobs carry no extra register per output
+        if (p.tvg) un = __fdiv_rn(un, p.tvg[q]);
         p.u[q] = un;
         if (p.cnt && p.thin_mode != THIN_OFF) {
             bool below = thin_below(un, e.x, p.thin_mode, p.tau);
