@@ -263,8 +263,8 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             int want = std::max(1, (m + 511) / 512);  // aim for >= 512 workgroups
             if (p->tuning.lines_per_wg > 0) want = p->tuning.lines_per_wg;
             cfg->lines_per_wg = std::max(1, std::min(std::min(by_threads, by_lds), want));
-            if (per_line > kLdsLimit) { *why = "line too long for LDS"; return RL_E_UNSUPPORTED; }
-            cfg->lds_a = cfg->lines_per_wg * per_line;
+            if (per_line + rlk::kResidentFlagWords * sizeof(float) > kLdsLimit) { *why = "line too long for LDS"; return RL_E_UNSUPPORTED; }
+            cfg->lds_a = cfg->lines_per_wg * per_line + rlk::kResidentFlagWords * sizeof(float);
             return RL_OK;
         }
         if (sched == RL_SCHED_RESIDENT) { *why = "line too long for the resident schedule"; return RL_E_UNSUPPORTED; }
@@ -357,7 +357,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         if (cfg->kind == KIND_RECT) {
             // tile plus the horizontal window sums of every tile row
             size_t ny = 64 + t.lane_max - t.lane_min, nx = cfg->TB + t.c_max - t.c_min;
-            b = (ny * (nx | 1) + ny * (size_t)(cfg->TB + 1)) * sizeof(float);
+            b = rlk::rect_lds_floats<kNW>((int)ny, (int)nx, cfg->TB) * sizeof(float);
         }
         return b;
     };

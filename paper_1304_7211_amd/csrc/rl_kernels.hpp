@@ -77,6 +77,16 @@ __device__ __forceinline__ int fold_idx(int i, int n, int bc) {
     return p < n ? p : m - 1 - p;
 }
 
+// 1 for a non-zero value, 0 for +0 and -0 (inputs are >= 0 apart from the sign of zero,
+// so min(bits << 1, 1) does it in integer ops).  Sliding sums keep an exact integer count
+// of the non-zero inputs in their window next to the float running sum: every input is
+// >= 0, so a window sum is exactly 0 iff the count is 0, which the float sum -- after
+// subtracting the larger values that left the window -- does not reproduce exactly.  Exact
+// zeros matter: v = 0 gives r = 0 where a near-zero v gives a huge ratio, and c = 0 gives
+// u^{k+1} = 0 exactly.  The counts are only kept in tiles whose inputs hold an exact zero
+// (tile_zeros below); elsewhere every window sum is positive anyway.
+__device__ __forceinline__ int nz(float x) { return (int)min(__float_as_uint(x) << 1, 1u); }
+
 // Kahan-compensated accumulation: s + x with running compensation c.
 __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     float y = x - c;
@@ -281,6 +291,30 @@ __device__ __forceinline__ void load_tile(float* lds, const float* __restrict__ 
 
 // Wait for this wavefront's outstanding global loads, including LDS DMA.
 __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Zero detection on a tile loaded by load_tile.  Called by every wavefront after its own
+// lds_dma_wait(): it scans exactly the rows and columns its own loads wrote (rows wv,
+// wv + nwv, ...; columns lane, lane + 64, ...) and publishes one flag word zf[wv] for the
+// workgroup barrier that follows; tile_zeros() then reads the OR of the flags (uniform).
+__device__ __forceinline__ void note_zeros(const float* lds, int ny, int nx, int pitch, int* zf) {
+    const int nwv = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    bool z = false;
+    for (int row = wv; row < ny; row += nwv) {
+        const float* r = lds + row * pitch;
+        for (int c = lane; c < nx; c += 64) z |= r[c] == 0.f;
+    }
+    const bool any = __ballot(z) != 0ull;
+    if (lane == 0) zf[wv] = any ? 1 : 0;
+}
+
+template <int NW>
+__device__ __forceinline__ bool tile_zeros(const int* zf) {
+    int o = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) o |= zf[w];
+    return __builtin_amdgcn_readfirstlane(o) != 0;
+}
 
 // Epilogue inputs of one output at linear position q: f (phase A) or u^k (phase B), and
 // the convergence counter in thinned mode.  Gathered for all outputs of a lane before any
@@ -554,19 +588,15 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 // then its start value from the seed parts and the preceding wavefronts' totals, exchanged
 // through LDS.  kahan = 0 uses plain float32 sums instead.
 // ---------------------------------------------------------------------------------------
+// exchange rows 0..5 (seed, its compensation, strip total, its compensation, seed count,
+// strip count), then the NW zero flags of note_zeros
 template <int NW>
-__host__ __device__ constexpr int slide_scratch_floats() { return 4 * NW * 64; }
+__host__ __device__ constexpr int slide_scratch_floats() { return 6 * NW * 64 + NW; }
 
-template <int ORIENT, int S, int NW, bool PHASE_B>
-__device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
-    constexpr int TA = 64, TB = NW * S;
-    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
-    EpiPlan<ORIENT, S, NW> plan;
-    epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
-    load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
-    lds_dma_wait();
-    __syncthreads();
-
+template <int ORIENT, int S, int NW, bool PHASE_B, bool COUNT>
+__device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, float* lds,
+                                           const TileGeom<ORIENT>& g,
+                                           const EpiPlan<ORIENT, S, NW>& plan) {
     const int lane = threadIdx.x & 63, wv = wave_id();
     const float* lane_lds = lds + g.lane_part(lane - p.lane_min);
     const int lb = wv * S - p.c_min;   // this wavefront's strip start
@@ -576,6 +606,7 @@ __device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, f
     const ConstSpanPtr spans = as_const(p.spans);
     // this wavefront's share of the seed: spans i with i % NW == wv, in increasing i
     float seed = 0.f, seed_c = 0.f;
+    int seed_n = 0;  // non-zero inputs in this wavefront's share of the seed windows
     for (int i = wv; i < p.n_spans; i += NW) {
         const DevSpan sp = load_span(spans, i);
         const float* base = lane_lds + g.uni_part(sp.lane_off, lb0 + sp.c0);
@@ -583,12 +614,19 @@ __device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, f
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         int q = 0;
         for (; q + 4 <= len; q += 4) {
-            p0 += base[q * st];
-            p1 += base[(q + 1) * st];
-            p2 += base[(q + 2) * st];
-            p3 += base[(q + 3) * st];
+            const float v0 = base[q * st], v1 = base[(q + 1) * st];
+            const float v2 = base[(q + 2) * st], v3 = base[(q + 3) * st];
+            p0 += v0;
+            p1 += v1;
+            p2 += v2;
+            p3 += v3;
+            if (COUNT) seed_n += (nz(v0) + nz(v1)) + (nz(v2) + nz(v3));
         }
-        for (; q < len; ++q) p0 += base[q * st];
+        for (; q < len; ++q) {
+            const float v0 = base[q * st];
+            p0 += v0;
+            if (COUNT) seed_n += nz(v0);
+        }
         const float part = (p0 + p1) + (p2 + p3);
         if (kahan) kahan_add(seed, seed_c, sp.w0 * part);
         else seed = fmaf(sp.w0, part, seed);
@@ -599,8 +637,9 @@ __device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, f
     // the seed): it reads an in-tile neighbour instead and is cleared afterwards.
     constexpr int U = S <= 8 ? 2 : 1;
     float d[S];
+    int dn[S];  // change of the non-zero count
 #pragma unroll
-    for (int s = 0; s < S; ++s) d[s] = 0.f;
+    for (int s = 0; s < S; ++s) { d[s] = 0.f; dn[s] = 0; }
     const int z0 = wv == 0 ? 1 : 0;
     int i = 0;
     for (; i + U <= p.n_spans; i += U) {
@@ -621,35 +660,49 @@ __device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, f
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < S; ++s) d[s] = fmaf(sp[u].w0, din[u][s] - dout[u][s], d[s]);
+            for (int s = 0; s < S; ++s) {
+                d[s] = fmaf(sp[u].w0, din[u][s] - dout[u][s], d[s]);
+                if (COUNT) dn[s] += nz(din[u][s]) - nz(dout[u][s]);
+            }
     }
     for (; i < p.n_spans; ++i) {
         const DevSpan sp = load_span(spans, i);
         const float* base = lane_lds + g.uni_part(sp.lane_off, lb + sp.c0);
         const float* bin = base + (sp.len - 1) * st;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            d[s] = fmaf(sp.w0, bin[s * st] - base[(s == 0 ? z0 - 1 : s - 1) * st], d[s]);
+        for (int s = 0; s < S; ++s) {
+            const float vin = bin[s * st], vout = base[(s == 0 ? z0 - 1 : s - 1) * st];
+            d[s] = fmaf(sp.w0, vin - vout, d[s]);
+            if (COUNT) dn[s] += nz(vin) - nz(vout);
+        }
     }
-    if (z0) d[0] = 0.f;
+    if (z0) { d[0] = 0.f; dn[0] = 0; }
     // prefix of the changes inside the strip (value P, compensation C: true sum = P - C)
     float P[S], C[S];
+    int Pn[S];
     {
         float run = 0.f, c = 0.f;
+        int rn = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (kahan) kahan_add(run, c, d[s]);
             else run += d[s];
             P[s] = run;
             C[s] = c;
+            rn += dn[s];
+            Pn[s] = rn;
         }
     }
-    // exchange seed parts and strip totals
+    // exchange seed parts and strip totals (values and non-zero counts)
     float* xs = lds + g.ny * g.pitch;
     xs[(0 * NW + wv) * 64 + lane] = seed;
     xs[(1 * NW + wv) * 64 + lane] = seed_c;
     xs[(2 * NW + wv) * 64 + lane] = P[S - 1];
     xs[(3 * NW + wv) * 64 + lane] = C[S - 1];
+    if (COUNT) {
+        xs[(4 * NW + wv) * 64 + lane] = __int_as_float(seed_n);
+        xs[(5 * NW + wv) * 64 + lane] = __int_as_float(Pn[S - 1]);
+    }
     __syncthreads();
     float base = 0.f, bc = 0.f;
 #pragma unroll
@@ -666,11 +719,35 @@ __device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, f
             else base += part;
         }
     }
+    int base_n = 0;
+    if (COUNT) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            base_n += __float_as_int(xs[(4 * NW + w) * 64 + lane]);
+            if (w < wv) base_n += __float_as_int(xs[(5 * NW + w) * 64 + lane]);
+        }
+    }
     const float b_true = base - bc;
     float out[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) out[s] = b_true + (P[s] - C[s]);
+    for (int s = 0; s < S; ++s)
+        out[s] = (COUNT && base_n + Pn[s] == 0) ? 0.f : b_true + (P[s] - C[s]);
     write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, out, plan);
+}
+
+template <int ORIENT, int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
+    constexpr int TA = 64, TB = NW * S;
+    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
+    EpiPlan<ORIENT, S, NW> plan;
+    epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
+    load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
+    lds_dma_wait();
+    int* zf = reinterpret_cast<int*>(lds + g.ny * g.pitch + 6 * NW * 64);
+    note_zeros(lds, g.ny, g.nx, g.pitch, zf);
+    __syncthreads();
+    if (tile_zeros<NW>(zf)) slide_body<ORIENT, S, NW, PHASE_B, true>(p, a0, b0, lds, g, plan);
+    else slide_body<ORIENT, S, NW, PHASE_B, false>(p, a0, b0, lds, g, plan);
 }
 
 template <int ORIENT, int S, int NW, bool PHASE_B>
@@ -702,51 +779,58 @@ __device__ __forceinline__ void rl_add(float& s, float& c, float x, bool kahan) 
     else s += x;
 }
 
-template <int S, int NW, bool PHASE_B>
-__device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
+// LDS after the tile: ny rows of TB horizontal window sums (pitch TB + 1), their non-zero
+// counts (same layout, int), then the NW zero flags of note_zeros
+template <int NW>
+__host__ __device__ constexpr size_t rect_lds_floats(int ny, int nx, int TB) {
+    return (size_t)ny * (nx | 1) + 2 * (size_t)ny * rect_hs_pitch<NW>(TB) + NW;
+}
+
+template <int S, int NW, bool PHASE_B, bool COUNT>
+__device__ __forceinline__ void rect_body(const PhaseArgs& p, int a0, int b0, float* lds,
+                                          const EpiIn (&in)[RECT_SEG]) {
     constexpr int TB = NW * S;
     constexpr int NSEG_H = TB / RECT_SEG;       // horizontal segments per tile row
     constexpr int NV = TB * (64 / RECT_SEG);    // vertical tasks (column, row segment)
-    static_assert(NV <= NW * 64, "one vertical task per thread");
     const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
     const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
-    float* hs = lds + ny * pitch;  // ny rows of TB horizontal sums (pitch TB + 1)
+    float* hs = lds + ny * pitch;
+    int* hn = reinterpret_cast<int*>(hs + ny * rect_hs_pitch<NW>(TB));
     const int tid = threadIdx.x;
     const bool kahan = p.kahan != 0;
-    // vertical task of this thread and its outputs' epilogue inputs (loaded up front)
     const int vb = tid % TB, vr = tid / TB;
     const bool has_v = tid < NV;
-    EpiIn in[RECT_SEG];
-    if (has_v) {
-#pragma unroll
-        for (int j = 0; j < RECT_SEG; ++j) {
-            const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
-            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
-        }
-    }
-    load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
-    lds_dma_wait();
-    __syncthreads();
     // horizontal pass
     for (int task = tid; task < ny * NSEG_H; task += NW * 64) {
         const int r = task / NSEG_H, c0 = (task % NSEG_H) * RECT_SEG;
         const float* row = lds + r * pitch + c0;
         float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        int n = 0;
         int t = 0;
         for (; t + 4 <= kw; t += 4) {
             q0 += row[t];
             q1 += row[t + 1];
             q2 += row[t + 2];
             q3 += row[t + 3];
+            if (COUNT) n += (nz(row[t]) + nz(row[t + 1])) + (nz(row[t + 2]) + nz(row[t + 3]));
         }
-        for (; t < kw; ++t) q0 += row[t];
+        for (; t < kw; ++t) {
+            q0 += row[t];
+            if (COUNT) n += nz(row[t]);
+        }
         float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
         float* out = hs + r * rect_hs_pitch<NW>(TB) + c0;
+        int* outn = hn + r * rect_hs_pitch<NW>(TB) + c0;
         out[0] = sum;
+        if (COUNT) outn[0] = n;
 #pragma unroll
         for (int j = 1; j < RECT_SEG; ++j) {
             rl_add(sum, comp, row[j + kw - 1] - row[j - 1], kahan);
             out[j] = sum - comp;
+            if (COUNT) {
+                n += nz(row[j + kw - 1]) - nz(row[j - 1]);
+                outn[j] = n;
+            }
         }
     }
     __syncthreads();
@@ -757,21 +841,29 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
     if (has_v) {
         const int hp = rect_hs_pitch<NW>(TB);
         const float* col = hs + (vr * RECT_SEG) * hp + vb;
+        const int* coln = hn + (vr * RECT_SEG) * hp + vb;
         float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        int n = 0;
         int i = 0;
         for (; i + 4 <= kh; i += 4) {
             q0 += col[i * hp];
             q1 += col[(i + 1) * hp];
             q2 += col[(i + 2) * hp];
             q3 += col[(i + 3) * hp];
+            if (COUNT)
+                n += (coln[i * hp] + coln[(i + 1) * hp]) + (coln[(i + 2) * hp] + coln[(i + 3) * hp]);
         }
-        for (; i < kh; ++i) q0 += col[i * hp];
+        for (; i < kh; ++i) {
+            q0 += col[i * hp];
+            if (COUNT) n += coln[i * hp];
+        }
         float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
-        v[0] = sum;
+        v[0] = (!COUNT || n) ? sum : 0.f;
 #pragma unroll
         for (int j = 1; j < RECT_SEG; ++j) {
             rl_add(sum, comp, col[(j + kh - 1) * hp] - col[(j - 1) * hp], kahan);
-            v[j] = sum - comp;
+            if (COUNT) n += coln[(j + kh - 1) * hp] - coln[(j - 1) * hp];
+            v[j] = (!COUNT || n) ? sum - comp : 0.f;
         }
     }
 #pragma unroll
@@ -783,6 +875,33 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
         if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
     }
     if (PHASE_B) add_active(p, n_active);
+}
+
+template <int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
+    constexpr int TB = NW * S;
+    constexpr int NV = TB * (64 / RECT_SEG);    // vertical tasks (column, row segment)
+    static_assert(NV <= NW * 64, "one vertical task per thread");
+    const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
+    const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
+    const int tid = threadIdx.x;
+    // vertical task of this thread and its outputs' epilogue inputs (loaded up front)
+    const int vb = tid % TB, vr = tid / TB;
+    EpiIn in[RECT_SEG];
+    if (tid < NV) {
+#pragma unroll
+        for (int j = 0; j < RECT_SEG; ++j) {
+            const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
+            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+        }
+    }
+    load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
+    lds_dma_wait();
+    int* zf = reinterpret_cast<int*>(lds + rect_lds_floats<NW>(ny, nx, TB) - NW);
+    note_zeros(lds, ny, nx, pitch, zf);
+    __syncthreads();
+    if (tile_zeros<NW>(zf)) rect_body<S, NW, PHASE_B, true>(p, a0, b0, lds, in);
+    else rect_body<S, NW, PHASE_B, false>(p, a0, b0, lds, in);
 }
 
 template <int S, int NW, bool PHASE_B>
@@ -1160,20 +1279,33 @@ __device__ __forceinline__ void line_store(float* line, int pos, int n, int halo
 // Window sums out[q] = sum_{t < len} line[p0 + q + c0 + t], q = 0..SEG-1 (halo-extended
 // line, no folds), by a sliding window seeded at q = 0.  All LDS reads are issued before
 // the dependent running sum.
-template <int SEG>
+// LDS words after the resident kernel's lines: zero flags, 4 wavefronts x (u, r)
+constexpr int kResidentFlagWords = 8;
+
+template <int SEG, bool COUNT>
 __device__ __forceinline__ void box_segment(const float* line, int halo, int p0, int c0,
                                             int len, bool kahan, float (&out)[SEG]) {
     const int lo = p0 + c0;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int n = 0;  // non-zero inputs in the window (exact zeros, see nz)
     int q = 0;
 #pragma unroll 1
     for (; q + 4 <= len; q += 4) {
-        s0 += line[line_idx<SEG>(lo + q, halo)];
-        s1 += line[line_idx<SEG>(lo + q + 1, halo)];
-        s2 += line[line_idx<SEG>(lo + q + 2, halo)];
-        s3 += line[line_idx<SEG>(lo + q + 3, halo)];
+        const float v0 = line[line_idx<SEG>(lo + q, halo)];
+        const float v1 = line[line_idx<SEG>(lo + q + 1, halo)];
+        const float v2 = line[line_idx<SEG>(lo + q + 2, halo)];
+        const float v3 = line[line_idx<SEG>(lo + q + 3, halo)];
+        s0 += v0;
+        s1 += v1;
+        s2 += v2;
+        s3 += v3;
+        if (COUNT) n += (nz(v0) + nz(v1)) + (nz(v2) + nz(v3));
     }
-    for (; q < len; ++q) s0 += line[line_idx<SEG>(lo + q, halo)];
+    for (; q < len; ++q) {
+        const float v0 = line[line_idx<SEG>(lo + q, halo)];
+        s0 += v0;
+        if (COUNT) n += nz(v0);
+    }
     float din[SEG], dout[SEG];
 #pragma unroll
     for (int q2 = 1; q2 < SEG; ++q2) {
@@ -1181,13 +1313,14 @@ __device__ __forceinline__ void box_segment(const float* line, int halo, int p0,
         dout[q2] = line[line_idx<SEG>(lo + q2 - 1, halo)];
     }
     float run = (s0 + s1) + (s2 + s3), c = 0.f;
-    out[0] = run;
+    out[0] = (!COUNT || n) ? run : 0.f;
 #pragma unroll
     for (int q2 = 1; q2 < SEG; ++q2) {
         float d = din[q2] - dout[q2];
         if (kahan) kahan_add(run, c, d);
         else run += d;
-        out[q2] = run;
+        if (COUNT) n += nz(din[q2]) - nz(dout[q2]);
+        out[q2] = (!COUNT || n) ? run : 0.f;
     }
 }
 
@@ -1207,6 +1340,20 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
     const int halo = a.halo;
     float* ul = lds + (size_t)j * 2 * a.line_words;
     float* rl = ul + a.line_words;
+    // zero flags per wavefront (after the lines): [0, 4) for u, [4, 8) for r.  Each phase
+    // keeps non-zero counts in its window sums only if the line values it reads (produced
+    // by the previous phase) hold an exact 0 somewhere in the workgroup.
+    int* zfl = reinterpret_cast<int*>(lds + (size_t)a.lines_per_wg * 2 * a.line_words);
+    const int lane = threadIdx.x & 63, wv = wave_id(), nwv = blockDim.x >> 6;
+    auto publish = [&](int* zf, bool z) {
+        const bool any = __ballot(z) != 0ull;
+        if (lane == 0) zf[wv] = any ? 1 : 0;
+    };
+    auto any_flag = [&](const int* zf) {
+        int o = 0;
+        for (int w = 0; w < nwv; ++w) o |= zf[w];
+        return __builtin_amdgcn_readfirstlane(o) != 0;
+    };
     const int p0 = t * SEG;
     const bool work = live && p0 < n;
 
@@ -1218,6 +1365,7 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
     for (int e = threadIdx.x; e < a.lines_per_wg * 2 * a.line_words; e += blockDim.x) lds[e] = 0.f;
     __syncthreads();
     float fr[SEG];
+    bool z = false;
     if (live) {
         float uv[SEG];
 #pragma unroll
@@ -1228,33 +1376,51 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < SEG; ++q)
-            if (p0 + q < n) line_store<SEG>(ul, p0 + q, n, halo, a.bc, uv[q]);
+            if (p0 + q < n) {
+                z |= uv[q] == 0.f;
+                line_store<SEG>(ul, p0 + q, n, halo, a.bc, uv[q]);
+            }
     }
+    publish(zfl, z);
     __syncthreads();
+    bool zu = any_flag(zfl);
     const bool kahan = a.kahan != 0;
 
     for (int it = 0; it < a.n_iter; ++it) {
+        z = false;
         if (work) {  // forward box + ratio
             float v[SEG];
-            box_segment<SEG>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
+            if (zu) box_segment<SEG, true>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
+            else box_segment<SEG, false>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
 #pragma unroll
             for (int q = 0; q < SEG; ++q)
-                if (p0 + q < n) line_store<SEG>(rl, p0 + q, n, halo, a.bc, rl_ratio(fr[q], a.w * v[q]));
+                if (p0 + q < n) {
+                    const float r = rl_ratio(fr[q], a.w * v[q]);
+                    z |= r == 0.f;
+                    line_store<SEG>(rl, p0 + q, n, halo, a.bc, r);
+                }
         }
+        publish(zfl + 4, z);
         __syncthreads();
+        const bool zr = any_flag(zfl + 4);
+        z = false;
         if (work) {  // adjoint box + multiplicative update
             float c[SEG];
-            box_segment<SEG>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
+            if (zr) box_segment<SEG, true>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
+            else box_segment<SEG, false>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
 #pragma unroll
             for (int q = 0; q < SEG; ++q) {
                 int pos = p0 + q;
                 if (pos < n) {
                     float un = __fmul_rn(ul[line_idx<SEG>(pos, halo)], a.w * c[q]);
+                    z |= un == 0.f;
                     line_store<SEG>(ul, pos, n, halo, a.bc, un);
                 }
             }
         }
+        publish(zfl, z);
         __syncthreads();
+        zu = any_flag(zfl);
     }
     if (live) {
 #pragma unroll

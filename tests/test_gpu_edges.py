@@ -1,0 +1,110 @@
+"""Edge cases of the GPU path against the FP64 oracle: the largest PSFs the ABI accepts
+(127 taps per side), a 4096 x 4096 image (the serving configuration's largest side),
+zeros in f and u^0 (v = 0 gives r = 0), PSFs inside zero margins, and constant images
+as fixed points."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import RTOL, rel_err, run_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def _obs(H, W, h, seed):
+    return synth.observe(synth.latent_image(H, W, seed), h, "poisson", seed)
+
+
+MAX_PSFS = [("box_h127", lambda: synth.box_h(127), ["box_axis", "runs"]),
+            ("box_v127", lambda: synth.box_v(127), ["box_axis", "runs"]),
+            ("disc63", lambda: synth.disc(63), ["runs"]),
+            ("dense127", lambda: synth.dense_random(127, 9), ["direct", "runs"]),
+            ("rect127x101", lambda: synth.box_rect(127, 101), ["box_rect"])]
+
+
+@pytest.mark.parametrize("name,mk,paths", MAX_PSFS, ids=[c[0] for c in MAX_PSFS])
+def test_largest_psfs(orc, name, mk, paths):
+    h = mk()
+    f = _obs(150, 170, h, 81)
+    ref = orc.rl(f, h, 3)
+    for path in paths:
+        scheds = ["two_pass", "resident"] if path == "box_axis" else ["auto"]
+        for sched in scheds:
+            u, info = run_gpu(f, h, 3, path=path, schedule=sched)
+            err = rel_err(u, ref)
+            print(f"{name} {path}/{sched}: {err:.3g} {info['strip']}")
+            assert err <= RTOL, (name, path, sched, err)
+
+
+@pytest.mark.slow
+def test_4096_square_image(orc):
+    h = synth.disc(5)
+    f = synth.observe(synth.latent_image(4096, 4096, 82), h, "gaussian", 82)
+    ref = orc.rl(f, h, 2)
+    u, info = run_gpu(f, h, 2)
+    assert rel_err(u, ref) <= RTOL
+    # and in a batch with a small job, bit-identical to running alone
+    from paper_1304_7211_amd.job import BatchRunner, Job
+    small = _obs(100, 90, h, 83)
+    jobs = [Job(to_dev(f), h), Job(to_dev(small), h)]
+    BatchRunner(2).iterate(jobs, [2, 5])
+    ub = jobs[0].result().cpu().numpy()
+    us = jobs[1].result().cpu().numpy()
+    for j in jobs:
+        j.close()
+    assert np.array_equal(ub, u.astype(np.float32))
+    alone, _ = run_gpu(small, h, 5)
+    assert np.array_equal(us, alone.astype(np.float32))
+
+
+ZERO_CASES = [("disc3", lambda: synth.disc(3), [("direct", "auto"), ("runs", "auto")]),
+              ("box_h9", lambda: synth.box_h(9), [("box_axis", "two_pass"),
+                                                  ("box_axis", "resident"), ("runs", "auto")]),
+              ("box_v7", lambda: synth.box_v(7), [("box_axis", "two_pass"),
+                                                  ("box_axis", "resident")]),
+              ("rect5x4", lambda: synth.box_rect(5, 4), [("box_rect", "auto"), ("runs", "auto")]),
+              ("oblique13", lambda: synth.oblique_line(13, 35.0), [("runs", "auto")])]
+
+
+@pytest.mark.parametrize("start", ["f", "flat"])
+@pytest.mark.parametrize("name,mk,paths", ZERO_CASES, ids=[c[0] for c in ZERO_CASES])
+def test_zeros_in_f_and_u0(orc, name, mk, paths, start):
+    """Exact zeros: windows whose inputs are all 0 must give exactly 0, also on the sliding
+    paths after the window has passed larger values: v = 0 -> r = 0 (forward sums), and
+    c = 0 -> u^{k+1} = 0 (adjoint sums; with a flat start u^0 is non-zero where f is 0)."""
+    h = mk()
+    f = _obs(90, 110, h, 84)
+    f[10:30, 20:50] = 0.0        # a black region: r = 0 there
+    f[50, :] = 0.0
+    u0 = f.copy() if start == "f" else np.full_like(f, np.float32(f.mean()))
+    u0[60:70, 60:80] = 0.0       # pixels that start at 0 stay 0; v = 0 inside the block
+    ref = orc.rl(f, h, 6, u0=u0)
+    for path, sched in paths:
+        u, _ = run_gpu(f, h, 6, path=path, schedule=sched, u0=to_dev(u0))
+        err = rel_err(u, ref)
+        print(f"{name} {path}/{sched}: {err:.3g}")
+        assert err <= RTOL, (path, sched, err)
+        assert np.all(u[60:70, 60:80] == 0.0)
+
+
+def test_psf_in_zero_margins(orc):
+    h = np.zeros((9, 11), np.float32)
+    h[2:5, 1:4] = synth.disc(1)
+    h = (h / h.sum()).astype(np.float32)
+    f = _obs(70, 80, synth.disc(1), 85)
+    ref = orc.rl(f, h, 5)
+    for path in ["direct", "runs"]:
+        u, _ = run_gpu(f, h, 5, path=path)
+        assert rel_err(u, ref) <= RTOL, path
+
+
+def test_constant_image_is_fixed_point():
+    for h in [synth.disc(6), synth.box_h(9), synth.box_rect(4, 5), synth.oblique_line(13, 20.0)]:
+        f = np.full((77, 91), 0.37, np.float32)
+        u, _ = run_gpu(f, h, 10)
+        # every path sums the normalised PSF to 1 within float32 rounding
+        assert np.max(np.abs(u - 0.37)) <= 1e-5 * 0.37, h.shape
