@@ -263,8 +263,8 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             int want = std::max(1, (m + 511) / 512);  // aim for >= 512 workgroups
             if (p->tuning.lines_per_wg > 0) want = p->tuning.lines_per_wg;
             cfg->lines_per_wg = std::max(1, std::min(std::min(by_threads, by_lds), want));
-            if (per_line + rlk::kResidentFlagWords * sizeof(float) > kLdsLimit) { *why = "line too long for LDS"; return RL_E_UNSUPPORTED; }
-            cfg->lds_a = cfg->lines_per_wg * per_line + rlk::kResidentFlagWords * sizeof(float);
+            if (per_line > kLdsLimit) { *why = "line too long for LDS"; return RL_E_UNSUPPORTED; }
+            cfg->lds_a = cfg->lines_per_wg * per_line;
             return RL_OK;
         }
         if (sched == RL_SCHED_RESIDENT) { *why = "line too long for the resident schedule"; return RL_E_UNSUPPORTED; }

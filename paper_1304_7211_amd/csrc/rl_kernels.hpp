@@ -296,15 +296,28 @@ __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0); 
 // lds_dma_wait(): it scans exactly the rows and columns its own loads wrote (rows wv,
 // wv + nwv, ...; columns lane, lane + 64, ...) and publishes one flag word zf[wv] for the
 // workgroup barrier that follows; tile_zeros() then reads the OR of the flags (uniform).
+// The scan keeps the minimum of |value| with eight reads in flight per step, so it costs
+// a few LDS round trips rather than one per row.
 __device__ __forceinline__ void note_zeros(const float* lds, int ny, int nx, int pitch, int* zf) {
     const int nwv = blockDim.x >> 6;
     const int lane = threadIdx.x & 63, wv = wave_id();
-    bool z = false;
-    for (int row = wv; row < ny; row += nwv) {
-        const float* r = lds + row * pitch;
-        for (int c = lane; c < nx; c += 64) z |= r[c] == 0.f;
+    float m = 1.f;
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        if (lane + 64 * c < nx) {
+            const float* col = lds + lane + 64 * c;
+            int row = wv;
+            for (; row + 7 * nwv < ny; row += 8 * nwv) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = fabsf(col[(row + i * nwv) * pitch]);
+                m = fminf(m, fminf(fminf(fminf(v[0], v[1]), fminf(v[2], v[3])),
+                                   fminf(fminf(v[4], v[5]), fminf(v[6], v[7]))));
+            }
+            for (; row < ny; row += nwv) m = fminf(m, fabsf(col[row * pitch]));
+        }
     }
-    const bool any = __ballot(z) != 0ull;
+    const bool any = __ballot(m == 0.f) != 0ull;
     if (lane == 0) zf[wv] = any ? 1 : 0;
 }
 
@@ -1279,48 +1292,61 @@ __device__ __forceinline__ void line_store(float* line, int pos, int n, int halo
 // Window sums out[q] = sum_{t < len} line[p0 + q + c0 + t], q = 0..SEG-1 (halo-extended
 // line, no folds), by a sliding window seeded at q = 0.  All LDS reads are issued before
 // the dependent running sum.
-// LDS words after the resident kernel's lines: zero flags, 4 wavefronts x (u, r)
-constexpr int kResidentFlagWords = 8;
+// Sliding 1-D box sums of SEG consecutive outputs of one line (window [p0 + c0 + q,
+// p0 + c0 + q + len) for output q), seed by a direct sum, slide Kahan-compensated.
+// Exact zeros: every input is >= 0, so a direct float sum is 0 iff all of its terms are,
+// but a slid sum is not.  The inputs at [lo + SEG - 1, lo + len) lie in all SEG windows,
+// and the seed sums them separately: if that sum is positive no window is all-zero and the
+// slide stands.  Otherwise (rare) the non-zero inputs are counted exactly along the slide
+// and windows without any are set to 0.
+template <int SEG>
+__device__ __forceinline__ float box_range_sum(const float* line, int halo, int lo, int q0, int q1) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int q = q0;
+#pragma unroll 1
+    for (; q + 4 <= q1; q += 4) {
+        s0 += line[line_idx<SEG>(lo + q, halo)];
+        s1 += line[line_idx<SEG>(lo + q + 1, halo)];
+        s2 += line[line_idx<SEG>(lo + q + 2, halo)];
+        s3 += line[line_idx<SEG>(lo + q + 3, halo)];
+    }
+    for (; q < q1; ++q) s0 += line[line_idx<SEG>(lo + q, halo)];
+    return (s0 + s1) + (s2 + s3);
+}
 
-template <int SEG, bool COUNT>
+template <int SEG>
 __device__ __forceinline__ void box_segment(const float* line, int halo, int p0, int c0,
                                             int len, bool kahan, float (&out)[SEG]) {
     const int lo = p0 + c0;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    int n = 0;  // non-zero inputs in the window (exact zeros, see nz)
-    int q = 0;
-#pragma unroll 1
-    for (; q + 4 <= len; q += 4) {
-        const float v0 = line[line_idx<SEG>(lo + q, halo)];
-        const float v1 = line[line_idx<SEG>(lo + q + 1, halo)];
-        const float v2 = line[line_idx<SEG>(lo + q + 2, halo)];
-        const float v3 = line[line_idx<SEG>(lo + q + 3, halo)];
-        s0 += v0;
-        s1 += v1;
-        s2 += v2;
-        s3 += v3;
-        if (COUNT) n += (nz(v0) + nz(v1)) + (nz(v2) + nz(v3));
-    }
-    for (; q < len; ++q) {
-        const float v0 = line[line_idx<SEG>(lo + q, halo)];
-        s0 += v0;
-        if (COUNT) n += nz(v0);
-    }
+    const int nh = min(SEG - 1, len);
+    const float head = box_range_sum<SEG>(line, halo, lo, 0, nh);
+    const float common = box_range_sum<SEG>(line, halo, lo, nh, len);
     float din[SEG], dout[SEG];
 #pragma unroll
     for (int q2 = 1; q2 < SEG; ++q2) {
         din[q2] = line[line_idx<SEG>(lo + q2 + len - 1, halo)];
         dout[q2] = line[line_idx<SEG>(lo + q2 - 1, halo)];
     }
-    float run = (s0 + s1) + (s2 + s3), c = 0.f;
-    out[0] = (!COUNT || n) ? run : 0.f;
+    float run = head + common, c = 0.f;
+    out[0] = run;
 #pragma unroll
     for (int q2 = 1; q2 < SEG; ++q2) {
         float d = din[q2] - dout[q2];
         if (kahan) kahan_add(run, c, d);
         else run += d;
-        if (COUNT) n += nz(din[q2]) - nz(dout[q2]);
-        out[q2] = (!COUNT || n) ? run : 0.f;
+        out[q2] = run;
+    }
+    if (!(len >= SEG && common > 0.f)) {
+        int n = 0;  // non-zero inputs in the window
+#pragma unroll 1
+        for (int t = 0; t < len; ++t) n += nz(line[line_idx<SEG>(lo + t, halo)]);
+        if (n == 0) out[0] = 0.f;
+#pragma unroll
+        for (int q2 = 1; q2 < SEG; ++q2) {
+            n += nz(line[line_idx<SEG>(lo + q2 + len - 1, halo)]) -
+                 nz(line[line_idx<SEG>(lo + q2 - 1, halo)]);
+            if (n == 0) out[q2] = 0.f;
+        }
     }
 }
 
@@ -1340,20 +1366,6 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
     const int halo = a.halo;
     float* ul = lds + (size_t)j * 2 * a.line_words;
     float* rl = ul + a.line_words;
-    // zero flags per wavefront (after the lines): [0, 4) for u, [4, 8) for r.  Each phase
-    // keeps non-zero counts in its window sums only if the line values it reads (produced
-    // by the previous phase) hold an exact 0 somewhere in the workgroup.
-    int* zfl = reinterpret_cast<int*>(lds + (size_t)a.lines_per_wg * 2 * a.line_words);
-    const int lane = threadIdx.x & 63, wv = wave_id(), nwv = blockDim.x >> 6;
-    auto publish = [&](int* zf, bool z) {
-        const bool any = __ballot(z) != 0ull;
-        if (lane == 0) zf[wv] = any ? 1 : 0;
-    };
-    auto any_flag = [&](const int* zf) {
-        int o = 0;
-        for (int w = 0; w < nwv; ++w) o |= zf[w];
-        return __builtin_amdgcn_readfirstlane(o) != 0;
-    };
     const int p0 = t * SEG;
     const bool work = live && p0 < n;
 
@@ -1365,7 +1377,6 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
     for (int e = threadIdx.x; e < a.lines_per_wg * 2 * a.line_words; e += blockDim.x) lds[e] = 0.f;
     __syncthreads();
     float fr[SEG];
-    bool z = false;
     if (live) {
         float uv[SEG];
 #pragma unroll
@@ -1376,51 +1387,33 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < SEG; ++q)
-            if (p0 + q < n) {
-                z |= uv[q] == 0.f;
-                line_store<SEG>(ul, p0 + q, n, halo, a.bc, uv[q]);
-            }
+            if (p0 + q < n) line_store<SEG>(ul, p0 + q, n, halo, a.bc, uv[q]);
     }
-    publish(zfl, z);
     __syncthreads();
-    bool zu = any_flag(zfl);
     const bool kahan = a.kahan != 0;
 
     for (int it = 0; it < a.n_iter; ++it) {
-        z = false;
         if (work) {  // forward box + ratio
             float v[SEG];
-            if (zu) box_segment<SEG, true>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
-            else box_segment<SEG, false>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
+            box_segment<SEG>(ul, halo, p0, a.conv_c0, a.len, kahan, v);
 #pragma unroll
             for (int q = 0; q < SEG; ++q)
-                if (p0 + q < n) {
-                    const float r = rl_ratio(fr[q], a.w * v[q]);
-                    z |= r == 0.f;
-                    line_store<SEG>(rl, p0 + q, n, halo, a.bc, r);
-                }
+                if (p0 + q < n) line_store<SEG>(rl, p0 + q, n, halo, a.bc, rl_ratio(fr[q], a.w * v[q]));
         }
-        publish(zfl + 4, z);
         __syncthreads();
-        const bool zr = any_flag(zfl + 4);
-        z = false;
         if (work) {  // adjoint box + multiplicative update
             float c[SEG];
-            if (zr) box_segment<SEG, true>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
-            else box_segment<SEG, false>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
+            box_segment<SEG>(rl, halo, p0, a.corr_c0, a.len, kahan, c);
 #pragma unroll
             for (int q = 0; q < SEG; ++q) {
                 int pos = p0 + q;
                 if (pos < n) {
                     float un = __fmul_rn(ul[line_idx<SEG>(pos, halo)], a.w * c[q]);
-                    z |= un == 0.f;
                     line_store<SEG>(ul, pos, n, halo, a.bc, un);
                 }
             }
         }
-        publish(zfl, z);
         __syncthreads();
-        zu = any_flag(zfl);
     }
     if (live) {
 #pragma unroll
