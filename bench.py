@@ -29,8 +29,8 @@ configuration:
      p50/p99 latency and throughput of the continuous-batching server against the plain
      one-at-a-time method on the same GPU;
   6  rectangle PSFs (5x7, 15x15, 31x31, 63x9) at 1024^2 and 2048^2, 100 iterations: the
-     separable BOX_RECT kernels against the per-row sliding runs, px-it/s, per-launch
-     kernel time and HBM fraction of the phase kernels.
+     separable BOX_RECT kernels and the summed-area BOX_SAT kernels against the per-row
+     sliding runs, px-it/s, per-launch kernel time and HBM fraction of the phase kernels.
 """
 import argparse
 import json
@@ -100,6 +100,8 @@ def algorithmic_flops_per_px(kind, info, phase_b):
         conv = 2.0 * info["n_spans"]
     elif kind == "rect":
         conv = 4.0  # separable 2-D box: add and subtract per pass
+    elif kind == "sat":
+        conv = 3.0  # summed-area table: three adds of four corners
     elif kind == "resident":
         conv = 2.0
     else:
@@ -255,6 +257,8 @@ def main():
                     return "resident"
                 if inf["path"] == A.RL_PATH_BOX_RECT:
                     return "rect"
+                if inf["path"] == A.RL_PATH_BOX_SAT:
+                    return "sat"
                 return "slide" if inf["lmax"] == 0 else ("direct" if inf["lmax"] == 1 else "span")
             covered = [j for j in jobs
                        if (job_kind(infos[j["name"]]) == kind
@@ -552,7 +556,7 @@ def report_serving(args, dev):
 def _timing_name(kernel):
     """Map a rocprofv3 kernel symbol to the library's timing-registry name."""
     import re
-    m = re.search(r"rlk::(slide|span|resident|rect|mixed)_kernel<([^>]*)>", kernel)
+    m = re.search(r"rlk::(slide|span|resident|rect|sat|mixed)_kernel<([^>]*)>", kernel)
     if not m:
         return None
     kind, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
@@ -634,7 +638,7 @@ def report_rect(args, dev):
             f = torch.from_numpy(synth.observe(synth.latent_image(side, side, 6), h,
                                                "gaussian", 6)).to(dev)
             row = dict(psf=f"{my}x{mx}", side=side)
-            for path in ("runs", "box_rect"):
+            for path in ("runs", "box_rect", "box_sat"):
                 j = Job(f, h, path=path)
                 j.iterate(3)
                 torch.cuda.synchronize()
@@ -647,10 +651,10 @@ def report_rect(args, dev):
                 j.iterate(10)
                 torch.cuda.synchronize()
                 A.rl_timing_enable(False)
-                kind = "rect" if path == "box_rect" else None
                 us = []
-                for nm in ("rect_conv_ratio", "rect_corr_update", "slide_conv_ratio",
-                           "slide_corr_update", "span_conv_ratio", "span_corr_update"):
+                for nm in ("rect_conv_ratio", "rect_corr_update", "sat_conv_ratio",
+                           "sat_corr_update", "slide_conv_ratio", "slide_corr_update",
+                           "span_conv_ratio", "span_corr_update"):
                     n, ms = A.rl_timing_read(nm)
                     if n:
                         us.append(1e3 * ms / n)
@@ -662,9 +666,10 @@ def report_rect(args, dev):
                                  hbm_frac=round(BYTES_PER_PX_PHASE * side * side / (avg * 1e-6)
                                                 / (PEAK_HBM_GBS * 1e9), 4))
             row["speedup"] = round(row["runs"]["us_per_it"] / row["box_rect"]["us_per_it"], 3)
+            row["speedup_sat"] = round(row["runs"]["us_per_it"] / row["box_sat"]["us_per_it"], 3)
             rows.append(row)
             log(f"report 6: {row}")
-    return {"report": "rectangle PSFs: separable BOX_RECT vs sliding runs",
+    return {"report": "rectangle PSFs: separable BOX_RECT and summed-area BOX_SAT vs sliding runs",
             "iterations": K, "rows": rows}
 
 

@@ -65,6 +65,11 @@ typedef int32_t rl_status;
 #define RL_PATH_BOX_RECT 4 /* kh x kw uniform rectangle (kh, kw >= 2): separable sliding
                               sums, rows then columns, on an LDS tile (2-D box filter,
                               Section 3); constant work per pixel in kh and kw            */
+#define RL_PATH_BOX_SAT 5  /* the same rectangles from 2-D cumulated sums (Section 3, the
+                              summed-area variant of the 2-D box filter): each window sum
+                              from four corners of a table built per LDS tile in FP64, with
+                              an exact integer count of non-zero inputs; constant work per
+                              pixel; RL_E_UNSUPPORTED when the tile's tables exceed LDS   */
 
 /* iteration schedule: how the per-iteration kernels are organised */
 #define RL_SCHED_AUTO 0

@@ -36,7 +36,7 @@ constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3, KIND_RECT = 4 };
+enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3, KIND_RECT = 4, KIND_SAT = 5 };
 
 // ---- kernel timing registry -----------------------------------------------------------
 struct TimedLaunch {
@@ -179,13 +179,13 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     const int H = p->height, W = p->width;
     const bool thin = p->thin.mode != RL_THIN_OFF;
     int path = p->path == RL_PATH_AUTO ? c.auto_path : p->path;
-    if (path < RL_PATH_DIRECT || path > RL_PATH_BOX_RECT) { *why = "unknown path"; return RL_E_INVAL; }
+    if (path < RL_PATH_DIRECT || path > RL_PATH_BOX_SAT) { *why = "unknown path"; return RL_E_INVAL; }
     if (path == RL_PATH_BOX_AXIS && !c.is_axis_box) {
         *why = "BOX_AXIS path needs a 1 x L or L x 1 uniform box PSF";
         return RL_E_INVAL;
     }
-    if (path == RL_PATH_BOX_RECT && !c.is_rect) {
-        *why = "BOX_RECT path needs a uniform rectangle of at least 2 x 2 taps";
+    if ((path == RL_PATH_BOX_RECT || path == RL_PATH_BOX_SAT) && !c.is_rect) {
+        *why = "BOX_RECT and BOX_SAT paths need a uniform rectangle of at least 2 x 2 taps";
         return RL_E_INVAL;
     }
     cfg->path = path;
@@ -293,9 +293,9 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         cfg->lmax = 1;
         cfg->conv = rl::build_tap_table(h, kh, kw, false);
         cfg->corr = rl::build_tap_table(h, kh, kw, true);
-    } else if (path == RL_PATH_BOX_RECT) {
-        if (slide_S != 4 && slide_S != 8) { *why = "BOX_RECT runs strips of 4 or 8"; return RL_E_UNSUPPORTED; }
-        cfg->kind = KIND_RECT;
+    } else if (path == RL_PATH_BOX_RECT || path == RL_PATH_BOX_SAT) {
+        if (slide_S != 4 && slide_S != 8) { *why = "BOX_RECT and BOX_SAT run strips of 4 or 8"; return RL_E_UNSUPPORTED; }
+        cfg->kind = path == RL_PATH_BOX_SAT ? KIND_SAT : KIND_RECT;
         cfg->orient = rlk::ORIENT_ROWS;
         cfg->S = slide_S;
         cfg->lmax = 0;
@@ -358,6 +358,11 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             // tile plus the horizontal window sums of every tile row
             size_t ny = 64 + t.lane_max - t.lane_min, nx = cfg->TB + t.c_max - t.c_min;
             b = rlk::rect_lds_floats<kNW>((int)ny, (int)nx, cfg->TB) * sizeof(float);
+        }
+        if (cfg->kind == KIND_SAT) {
+            // tile plus the FP64 summed-area table and its non-zero counts
+            int ny = 64 + t.lane_max - t.lane_min, nx = cfg->TB + t.c_max - t.c_min;
+            b = rlk::sat_lds_bytes<kNW>(ny, nx);
         }
         return b;
     };
@@ -630,6 +635,11 @@ PhaseFn phase_fn(const Config& c, bool phase_b) {
         if (c.S == 8) return phase_b ? rlk::rect_kernel<8, kNW, true> : rlk::rect_kernel<8, kNW, false>;
         return nullptr;
     }
+    if (c.kind == KIND_SAT) {
+        if (c.S == 4) return phase_b ? rlk::sat_kernel<4, kNW, true> : rlk::sat_kernel<4, kNW, false>;
+        if (c.S == 8) return phase_b ? rlk::sat_kernel<8, kNW, true> : rlk::sat_kernel<8, kNW, false>;
+        return nullptr;
+    }
     if (c.kind == KIND_SPAN) {
         if (c.orient == rlk::ORIENT_ROWS)
             return phase_b ? span_fn_s<rlk::ORIENT_ROWS, true>(c.S, c.lmax)
@@ -644,6 +654,7 @@ PhaseFn phase_fn(const Config& c, bool phase_b) {
 
 const char* phase_name(const Config& c, bool phase_b) {
     if (c.kind == KIND_RECT) return phase_b ? "rect_corr_update" : "rect_conv_ratio";
+    if (c.kind == KIND_SAT) return phase_b ? "sat_corr_update" : "sat_conv_ratio";
     if (c.kind == KIND_SPAN)
         return phase_b ? (c.lmax == 1 ? "direct_corr_update" : "span_corr_update")
                        : (c.lmax == 1 ? "direct_conv_ratio" : "span_conv_ratio");

@@ -792,11 +792,14 @@ __device__ __forceinline__ void rl_add(float& s, float& c, float x, bool kahan) 
     else s += x;
 }
 
-// LDS after the tile: ny rows of TB horizontal window sums (pitch TB + 1), their non-zero
-// counts (same layout, int), then the NW zero flags of note_zeros
+// LDS after the tile: ny rows of TB horizontal window sums (pitch TB + 1), then the NW
+// zero flags of note_zeros.  Exact zeros (tiles holding a zero only): the horizontal pass
+// counts the non-zero inputs of each window and stores exactly 0 for windows without any,
+// so a vertical window is all-zero iff all its horizontal sums are 0, which the vertical
+// pass counts the same way.
 template <int NW>
 __host__ __device__ constexpr size_t rect_lds_floats(int ny, int nx, int TB) {
-    return (size_t)ny * (nx | 1) + 2 * (size_t)ny * rect_hs_pitch<NW>(TB) + NW;
+    return (size_t)ny * (nx | 1) + (size_t)ny * rect_hs_pitch<NW>(TB) + NW;
 }
 
 template <int S, int NW, bool PHASE_B, bool COUNT>
@@ -808,7 +811,6 @@ __device__ __forceinline__ void rect_body(const PhaseArgs& p, int a0, int b0, fl
     const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
     const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
     float* hs = lds + ny * pitch;
-    int* hn = reinterpret_cast<int*>(hs + ny * rect_hs_pitch<NW>(TB));
     const int tid = threadIdx.x;
     const bool kahan = p.kahan != 0;
     const int vb = tid % TB, vr = tid / TB;
@@ -833,17 +835,12 @@ __device__ __forceinline__ void rect_body(const PhaseArgs& p, int a0, int b0, fl
         }
         float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
         float* out = hs + r * rect_hs_pitch<NW>(TB) + c0;
-        int* outn = hn + r * rect_hs_pitch<NW>(TB) + c0;
-        out[0] = sum;
-        if (COUNT) outn[0] = n;
+        out[0] = (!COUNT || n) ? sum : 0.f;
 #pragma unroll
         for (int j = 1; j < RECT_SEG; ++j) {
             rl_add(sum, comp, row[j + kw - 1] - row[j - 1], kahan);
-            out[j] = sum - comp;
-            if (COUNT) {
-                n += nz(row[j + kw - 1]) - nz(row[j - 1]);
-                outn[j] = n;
-            }
+            if (COUNT) n += nz(row[j + kw - 1]) - nz(row[j - 1]);
+            out[j] = (!COUNT || n) ? sum - comp : 0.f;
         }
     }
     __syncthreads();
@@ -854,28 +851,29 @@ __device__ __forceinline__ void rect_body(const PhaseArgs& p, int a0, int b0, fl
     if (has_v) {
         const int hp = rect_hs_pitch<NW>(TB);
         const float* col = hs + (vr * RECT_SEG) * hp + vb;
-        const int* coln = hn + (vr * RECT_SEG) * hp + vb;
         float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
         int n = 0;
         int i = 0;
         for (; i + 4 <= kh; i += 4) {
-            q0 += col[i * hp];
-            q1 += col[(i + 1) * hp];
-            q2 += col[(i + 2) * hp];
-            q3 += col[(i + 3) * hp];
-            if (COUNT)
-                n += (coln[i * hp] + coln[(i + 1) * hp]) + (coln[(i + 2) * hp] + coln[(i + 3) * hp]);
+            const float h0 = col[i * hp], h1 = col[(i + 1) * hp];
+            const float h2 = col[(i + 2) * hp], h3 = col[(i + 3) * hp];
+            q0 += h0;
+            q1 += h1;
+            q2 += h2;
+            q3 += h3;
+            if (COUNT) n += (nz(h0) + nz(h1)) + (nz(h2) + nz(h3));
         }
         for (; i < kh; ++i) {
             q0 += col[i * hp];
-            if (COUNT) n += coln[i * hp];
+            if (COUNT) n += nz(col[i * hp]);
         }
         float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
         v[0] = (!COUNT || n) ? sum : 0.f;
 #pragma unroll
         for (int j = 1; j < RECT_SEG; ++j) {
-            rl_add(sum, comp, col[(j + kh - 1) * hp] - col[(j - 1) * hp], kahan);
-            if (COUNT) n += coln[(j + kh - 1) * hp] - coln[(j - 1) * hp];
+            const float hin = col[(j + kh - 1) * hp], hout = col[(j - 1) * hp];
+            rl_add(sum, comp, hin - hout, kahan);
+            if (COUNT) n += nz(hin) - nz(hout);
             v[j] = (!COUNT || n) ? sum - comp : 0.f;
         }
     }
@@ -924,6 +922,177 @@ __global__ __launch_bounds__(NW * 64) void rect_kernel(LaunchArgs L) {
     PhaseArgs p;
     if (!resolve<PHASE_B>(L, p, 64, NW * S, a0, b0)) return;
     rect_tile<S, NW, PHASE_B>(p, a0, b0, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// Summed-area-table kernel (2-D box filter from 2-D cumulated sums): the same operator as
+// the rectangle kernel, evaluated as in the paper's cumulated-sum variant -- every window
+// sum is T(a+kh, b+kw) - T(a, b+kw) - T(a+kh, b) + T(a, b) of the table T of cumulated sums
+// -- but with T built per tile in LDS instead of over the whole image: the tile's rows are
+// prefix-summed (one thread per row), then its columns (one thread per column).  T is held
+// in FP64: its entries grow with the tile's total, and a float32 table would lose the small
+// windows to cancellation.  Exact zeros (tiles holding a zero only): the row pass also
+// overwrites each tile value with the running count of non-zero values of its row (the
+// value itself is not needed afterwards), the column pass turns those into 2-D counts, and
+// windows with a zero count give exactly 0.  Work per output is constant in kh and kw:
+// four corner reads and three FP64 adds.
+// ---------------------------------------------------------------------------------------
+__host__ __device__ constexpr int sat_pitch(int nx) { return (nx + 1) | 1; }
+
+// LDS layout in bytes: float tile (ny x pitch; count table in place), FP64 table
+// ((ny + 1) x sat_pitch) at an 8-byte boundary, then the NW zero flags of note_zeros.
+__host__ __device__ constexpr size_t sat_table_offset(int ny, int nx) {
+    return (((size_t)ny * (nx | 1) * 4 + 7) / 8) * 8;
+}
+template <int NW>
+__host__ __device__ constexpr size_t sat_lds_bytes(int ny, int nx) {
+    return sat_table_offset(ny, nx) + (size_t)(ny + 1) * sat_pitch(nx) * 8 + NW * 4;
+}
+
+template <int S, int NW, bool PHASE_B, bool COUNT>
+__device__ __forceinline__ void sat_body(const PhaseArgs& p, int a0, int b0, float* lds,
+                                         const EpiIn (&in)[RECT_SEG]) {
+    constexpr int TB = NW * S;
+    constexpr int NV = TB * (64 / RECT_SEG);
+    const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
+    const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1, tp = sat_pitch(nx);
+    double* T = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + sat_table_offset(ny, nx));
+    int* N = reinterpret_cast<int*>(lds);  // inclusive counts, in place of the tile
+    const int tid = threadIdx.x;
+    // row 0 of T is 0; each row's prefix starts at column 0 = 0
+    for (int j = tid; j <= nx; j += NW * 64) T[j] = 0.0;
+    // row prefix sums: T(i + 1, j + 1) = sum of tile row i, columns 0..j
+    for (int i = tid; i < ny; i += NW * 64) {
+        const float* row = lds + i * pitch;
+        int* nrow = N + i * pitch;
+        double* trow = T + (size_t)(i + 1) * tp;
+        double s = 0.0;
+        int n = 0;
+        trow[0] = 0.0;
+        int j = 0;
+        for (; j + 4 <= nx; j += 4) {
+            const float v0 = row[j], v1 = row[j + 1], v2 = row[j + 2], v3 = row[j + 3];
+            s += (double)v0;
+            trow[j + 1] = s;
+            s += (double)v1;
+            trow[j + 2] = s;
+            s += (double)v2;
+            trow[j + 3] = s;
+            s += (double)v3;
+            trow[j + 4] = s;
+            if (COUNT) {
+                n += nz(v0);
+                nrow[j] = n;
+                n += nz(v1);
+                nrow[j + 1] = n;
+                n += nz(v2);
+                nrow[j + 2] = n;
+                n += nz(v3);
+                nrow[j + 3] = n;
+            }
+        }
+        for (; j < nx; ++j) {
+            const float v = row[j];
+            s += (double)v;
+            trow[j + 1] = s;
+            if (COUNT) {
+                n += nz(v);
+                nrow[j] = n;
+            }
+        }
+    }
+    __syncthreads();
+    // column prefix sums: T(i, j) becomes the sum over tile rows < i and columns < j;
+    // N(i, j) the count over tile rows <= i and columns <= j
+    for (int j = 1 + tid; j <= nx; j += NW * 64) {
+        double s = 0.0;
+        int i = 1;
+        for (; i + 4 <= ny + 1; i += 4) {
+            const double t0 = T[(size_t)i * tp + j], t1 = T[(size_t)(i + 1) * tp + j];
+            const double t2 = T[(size_t)(i + 2) * tp + j], t3 = T[(size_t)(i + 3) * tp + j];
+            s += t0;
+            T[(size_t)i * tp + j] = s;
+            s += t1;
+            T[(size_t)(i + 1) * tp + j] = s;
+            s += t2;
+            T[(size_t)(i + 2) * tp + j] = s;
+            s += t3;
+            T[(size_t)(i + 3) * tp + j] = s;
+        }
+        for (; i <= ny; ++i) {
+            s += T[(size_t)i * tp + j];
+            T[(size_t)i * tp + j] = s;
+        }
+        if (COUNT) {
+            int* c = N + (j - 1);
+            int n = 0;
+            for (int r = 0; r < ny; ++r) {
+                n += c[r * pitch];
+                c[r * pitch] = n;
+            }
+        }
+    }
+    __syncthreads();
+    // outputs from four corners: thread task (column vb, rows vr*8 .. vr*8+7)
+    const int vb = tid % TB, vr = tid / TB;
+    const bool has_v = tid < NV;
+    const float w = as_const(p.spans)[0].w0;
+    auto cnt_at = [&](int i, int j) { return (i < 0 || j < 0) ? 0 : N[i * pitch + j]; };
+    int n_active = 0;
+#pragma unroll
+    for (int j = 0; j < RECT_SEG; ++j) {
+        int act = 0;
+        const int a = vr * RECT_SEG + j;
+        const int y = a0 + a, x = b0 + vb;
+        if (has_v && y < p.H && x < p.W) {
+            const size_t r0 = (size_t)a * tp, r1 = (size_t)(a + kh) * tp;
+            const double sum = (T[r1 + vb + kw] - T[r0 + vb + kw]) - (T[r1 + vb] - T[r0 + vb]);
+            float v = (float)sum;
+            if (COUNT) {
+                const int n = (cnt_at(a + kh - 1, vb + kw - 1) - cnt_at(a - 1, vb + kw - 1)) -
+                              (cnt_at(a + kh - 1, vb - 1) - cnt_at(a - 1, vb - 1));
+                if (n == 0) v = 0.f;
+            }
+            act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, in[j], w * v);
+        }
+        if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+    }
+    if (PHASE_B) add_active(p, n_active);
+}
+
+template <int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
+    constexpr int TB = NW * S;
+    constexpr int NV = TB * (64 / RECT_SEG);
+    static_assert(NV <= NW * 64, "one output task per thread");
+    const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
+    const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
+    const int tid = threadIdx.x;
+    const int vb = tid % TB, vr = tid / TB;
+    EpiIn in[RECT_SEG];
+    if (tid < NV) {
+#pragma unroll
+        for (int j = 0; j < RECT_SEG; ++j) {
+            const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
+            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+        }
+    }
+    load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
+    lds_dma_wait();
+    int* zf = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + sat_lds_bytes<NW>(ny, nx)) - NW;
+    note_zeros(lds, ny, nx, pitch, zf);
+    __syncthreads();
+    if (tile_zeros<NW>(zf)) sat_body<S, NW, PHASE_B, true>(p, a0, b0, lds, in);
+    else sat_body<S, NW, PHASE_B, false>(p, a0, b0, lds, in);
+}
+
+template <int S, int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void sat_kernel(LaunchArgs L) {
+    extern __shared__ float lds[];
+    int a0, b0;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, 64, NW * S, a0, b0)) return;
+    sat_tile<S, NW, PHASE_B>(p, a0, b0, lds);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -152,6 +152,13 @@ def test_workspace_bytes_and_validation(A):
     p, k13 = _params(A, thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
     p.tv_lambda, p.tv_eps = 0.1, 1e-3
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    # summed-area rectangles: rectangle PSFs only, tables must fit in LDS
+    p, k14 = _params(A, psf=synth.box_rect(5, 7), path=A.RL_PATH_BOX_SAT)
+    assert _ws_status(A, p)[0] == A.RL_OK
+    p, k15 = _params(A, psf=synth.disc(3), path=A.RL_PATH_BOX_SAT)
+    assert _ws_status(A, p)[0] == A.RL_E_INVAL
+    p, k16 = _params(A, psf=synth.box_rect(127, 101), path=A.RL_PATH_BOX_SAT)
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
     # the persistent schedule is switched off
     p, k10 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT)
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED

@@ -32,6 +32,7 @@ def _mixed_jobs():
         ("obl15_thin", 120, 90, synth.oblique_line(15, 60.0), dict(thin=THIN), 16),
         ("rect9x5", 170, 140, synth.box_rect(9, 5), {}, 10),
         ("rect4x4_thin", 133, 97, synth.box_rect(4, 4), dict(thin=THIN), 15),
+        ("sat7x3", 150, 120, synth.box_rect(7, 3), dict(path="box_sat"), 9),
     ]
     out = []
     for i, (name, H, W, h, kw, K) in enumerate(spec):

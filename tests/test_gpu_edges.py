@@ -23,7 +23,8 @@ MAX_PSFS = [("box_h127", lambda: synth.box_h(127), ["box_axis", "runs"]),
             ("box_v127", lambda: synth.box_v(127), ["box_axis", "runs"]),
             ("disc63", lambda: synth.disc(63), ["runs"]),
             ("dense127", lambda: synth.dense_random(127, 9), ["direct", "runs"]),
-            ("rect127x101", lambda: synth.box_rect(127, 101), ["box_rect"])]
+            ("rect127x101", lambda: synth.box_rect(127, 101), ["box_rect"]),
+            ("rect63x41", lambda: synth.box_rect(63, 41), ["box_sat"])]
 
 
 @pytest.mark.parametrize("name,mk,paths", MAX_PSFS, ids=[c[0] for c in MAX_PSFS])
@@ -66,7 +67,8 @@ ZERO_CASES = [("disc3", lambda: synth.disc(3), [("direct", "auto"), ("runs", "au
                                                   ("box_axis", "resident"), ("runs", "auto")]),
               ("box_v7", lambda: synth.box_v(7), [("box_axis", "two_pass"),
                                                   ("box_axis", "resident")]),
-              ("rect5x4", lambda: synth.box_rect(5, 4), [("box_rect", "auto"), ("runs", "auto")]),
+              ("rect5x4", lambda: synth.box_rect(5, 4), [("box_rect", "auto"), ("box_sat", "auto"),
+                                                         ("runs", "auto")]),
               ("oblique13", lambda: synth.oblique_line(13, 35.0), [("runs", "auto")])]
 
 

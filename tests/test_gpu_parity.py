@@ -40,11 +40,11 @@ CASES = [
     ("oblique31", lambda: synth.oblique_line(31, 30.0), ["direct", "runs"]),
     ("oblique47_steep", lambda: synth.oblique_line(47, 75.0), ["runs"]),
     ("dense15", lambda: synth.dense_random(15, 2), ["direct", "runs"]),
-    ("rect5x7", lambda: synth.box_rect(5, 7), ["runs", "box_rect"]),
-    ("rect4x6_even", lambda: synth.box_rect(4, 6), ["direct", "box_rect"]),
-    ("rect2x2", lambda: synth.box_rect(2, 2), ["box_rect"]),
-    ("rect31x17", lambda: synth.box_rect(31, 17), ["runs", "box_rect"]),
-    ("rect_margin", lambda: np.pad(synth.box_rect(3, 6), ((2, 0), (0, 3))), ["box_rect"]),
+    ("rect5x7", lambda: synth.box_rect(5, 7), ["runs", "box_rect", "box_sat"]),
+    ("rect4x6_even", lambda: synth.box_rect(4, 6), ["direct", "box_rect", "box_sat"]),
+    ("rect2x2", lambda: synth.box_rect(2, 2), ["box_rect", "box_sat"]),
+    ("rect31x17", lambda: synth.box_rect(31, 17), ["runs", "box_rect", "box_sat"]),
+    ("rect_margin", lambda: np.pad(synth.box_rect(3, 6), ((2, 0), (0, 3))), ["box_rect", "box_sat"]),
 ]
 
 
@@ -73,7 +73,7 @@ def test_tiny_deep_folds(orc, shape):
         f = np.maximum(f, 0.05).astype(np.float32)
         ref = orc.rl(f, h, 4)
         for path in (["direct", "runs"] + (["box_axis"] if min(h.shape) == 1 else [])
-                     + (["box_rect"] if min(h.shape) > 1 and h.min() > 0 else [])):
+                     + (["box_rect", "box_sat"] if min(h.shape) > 1 and h.min() > 0 else [])):
             u, _ = run_gpu(f, h, 4, path=path)
             assert rel_err(u, ref) <= RTOL, (shape, h.shape, path)
 
@@ -92,7 +92,7 @@ def test_integer_images_bit_exact(orc):
         assert np.array_equal(fb.astype(np.float64), orc.conv(f.astype(np.float64), h01))
         rect = min(h01.shape) > 1 and h01.min() > 0
         for path in (["direct", "runs"] + (["box_axis"] if min(h01.shape) == 1 else [])
-                     + (["box_rect"] if rect else [])):
+                     + (["box_rect", "box_sat"] if rect else [])):
             scheds = ["two_pass", "resident"] if path == "box_axis" else ["auto"]
             for sched in scheds:
                 u, _ = run_gpu(fb, h01, 1, path=path, schedule=sched, u0=to_dev(f))

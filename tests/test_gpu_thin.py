@@ -66,13 +66,15 @@ def test_lockstep_one_iteration(orc, thin, k0):
     _lockstep(orc, thin, k0, synth.disc(4))
 
 
+@pytest.mark.parametrize("path", ["box_rect", "box_sat"])
 @pytest.mark.parametrize("k0", [10, 11, 13])
-def test_lockstep_rectangle(orc, k0):
-    """The separable rectangle kernel under thinning (tile list, per-pixel skipping)."""
-    _lockstep(orc, REL, k0, synth.box_rect(5, 7))
+def test_lockstep_rectangle(orc, k0, path):
+    """The rectangle kernels (separable and summed-area) under thinning (tile list,
+    per-pixel skipping)."""
+    _lockstep(orc, REL, k0, synth.box_rect(5, 7), path=path)
 
 
-def _lockstep(orc, thin, k0, h):
+def _lockstep(orc, thin, k0, h, path="auto"):
     f = synth.observe(synth.latent_image(150, 131, 31), h, "poisson", 31)
     u32, r32, cnt = _oracle_state(orc, f, h, thin, k0)
     # oracle side: one step from the float32 state
@@ -84,7 +86,7 @@ def _lockstep(orc, thin, k0, h):
     n_act = orc.thin_step(f, u, r, c, h, k0, thin)
     assert n_act == int(active.sum())
     # GPU side
-    job = Job(to_dev(f), h, thin=thin)
+    job = Job(to_dev(f), h, thin=thin, path=path)
     job.set_state(u=to_dev(u32), r=to_dev(r32), cnt=to_dev(cnt), k=k0)
     job.iterate(1)
     st = job.get_state()

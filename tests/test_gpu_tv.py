@@ -29,7 +29,7 @@ EPS, LAM = 2e-2, 4e-3
 CASES = [("disc6", lambda: synth.disc(6), ["runs", "direct"]),
          ("oblique21", lambda: synth.oblique_line(21, 40.0), ["runs"]),
          ("box_h15", lambda: synth.box_h(15), ["box_axis"]),
-         ("rect5x7", lambda: synth.box_rect(5, 7), ["box_rect"]),
+         ("rect5x7", lambda: synth.box_rect(5, 7), ["box_rect", "box_sat"]),
          ("dense9", lambda: synth.dense_random(9, 3), ["direct", "runs"])]
 
 
