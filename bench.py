@@ -130,11 +130,20 @@ def main():
                          "WRITE_SIZE) of a run with --calibrate-copy into the traffic "
                          "summary (markdown) on stdout")
     ap.add_argument("--pmc-command", default="",
-                    help="--summarize-pmc: the profiled command, quoted in the summary")
+                    help="--summarize-pmc / --summarize-trace: the profiled command, quoted "
+                         "in the summary")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
+                    help="no GPU work: turn a rocprofv3 --kernel-trace --stats CSV output "
+                         "and the JSON line of an unprofiled bench run into the kernel "
+                         "trace summary (markdown) on stdout")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
                             args.calibrate_copy, args.pmc_command))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace[0], args.summarize_trace[1],
+                              args.pmc_command))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -566,6 +575,37 @@ def _timing_name(kernel):
     if kind == "span" and targs[2] == "1":
         kind = "direct"
     return f"{kind}_{'corr_update' if phase_b else 'conv_ratio'}"
+
+
+def summarize_trace(trace_dir, bench_log, command):
+    """Per-kernel durations from rocprofv3's kernel statistics, next to bench.py's own
+    dispatch-event durations of an unprofiled run of the same workload."""
+    import csv
+    import glob
+    fn = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
+    rows = list(csv.DictReader(open(fn)))
+    line = [ln for ln in open(bench_log).read().splitlines() if ln.startswith("{")][-1]
+    bench = json.loads(line)
+    out = ["# Kernel trace: bench.py default workload (specialised PSFs, 3 x 1024x1024, "
+           "200 iterations, batch mode)", "", "Command:", "", "```", command.strip(), "```", "",
+           "The run covers bench.py's warmup step, its timed steps and its instrumented "
+           "steps. rocprofv3 lengthens the uninstrumented timing, so the headline value "
+           "comes from runs without the profiler.", "",
+           "| Kernel | calls | total ms | avg us | min us | max us | % |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    out += ["", "bench.py's own per-kernel durations (dispatch-attached events, same workload, "
+            "same box, run without the profiler just before):", ""]
+    for k, v in bench.get("kernels", {}).items():
+        out.append(f"- `{k}`: {v['avg_us']:.2f} us over {v['launches']} launches")
+    rf = bench.get("roofline") or {}
+    out += ["", f"Headline of that run: {bench['value']:.4g} {bench['unit']}, "
+            f"{bench['ms_per_step']:.3f} ms per step; roofline of `{rf.get('kernel')}`: "
+            f"{rf.get('achieved')} {rf.get('unit')} = {rf.get('frac')} of {rf.get('peak')}."]
+    return "\n".join(out)
 
 
 def summarize_pmc(fetch_dir, write_dir, copy_mib, command):
