@@ -505,6 +505,23 @@ rl_status dev_err(hipError_t e, const char* what) {
     return RL_E_DEVICE;
 }
 
+// Raise a kernel's dynamic LDS limit once per device and size (the runtime call costs
+// several microseconds, too much to repeat on every launch of a short kernel).
+std::mutex g_lds_mu;
+std::map<std::pair<int, const void*>, size_t> g_lds_set;
+
+hipError_t allow_lds(const void* fn, size_t lds) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(g_lds_mu);
+    size_t& have = g_lds_set[{dev, fn}];
+    if (have >= lds) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) have = lds;
+    return e;
+}
+
 template <typename... KArgs, typename... Args>
 hipError_t launch(const char* name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
                   size_t lds, hipStream_t s, Args... args) {
@@ -515,8 +532,7 @@ hipError_t launch(const char* name, void (*kernel)(KArgs...), dim3 grid, dim3 bl
         timed = g_timing;
     }
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = allow_lds(reinterpret_cast<const void*>(kernel), lds);
         if (e != hipSuccess) return e;
     }
     if (!timed) {
@@ -618,9 +634,7 @@ int persist_capacity(PersistFn fn, size_t lds) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds > 64 * 1024) (void)allow_lds(reinterpret_cast<const void*>(fn), lds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
                                                      kNW * 64, lds) != hipSuccess)
         return 0;
@@ -703,6 +717,16 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     a.full = 1;
     a.list_ok = 1;
     a.tvg = (phase_b && j->p.tv_lambda > 0.f) ? j->at<float>(j->L.tvg) : nullptr;
+    // the sliding kernel's exact-zero witness: the longest run, if it covers a strip
+    a.wit = -1;
+    if (c.kind == KIND_SLIDE) {
+        int best = 0;
+        for (size_t i = 0; i < t.spans.size(); ++i)
+            if (t.spans[i].len >= c.S && t.spans[i].len > best) {
+                best = t.spans[i].len;
+                a.wit = (int32_t)i;
+            }
+    }
     if (j->p.thin.mode != RL_THIN_OFF) {
         a.cnt = j->at<uint8_t>(j->L.cnt);
         a.thin_mode = j->p.thin.mode;

@@ -135,6 +135,7 @@ struct PhaseArgs {
     int32_t* act_part;             // 2 banks x ACT_SLOTS partial active counts
     int64_t k;                     // base iteration index (plus LaunchArgs::kb)
     const float* tvg;              // phase B: TV denominator 1 - lambda div(...) or NULL
+    int32_t wit;                   // sliding kernel: a span at least one strip long, or -1
 };
 
 // One launch covers the tiles of n_jobs jobs: job j owns workgroups
@@ -162,6 +163,7 @@ __device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
     p.full = t->full; p.tau = t->tau; p.list_ok = t->list_ok;
     p.sched = t->sched; p.active_total = t->active_total; p.act_part = t->act_part; p.k = t->k;
     p.tvg = t->tvg;
+    p.wit = t->wit;
     return p;
 }
 
@@ -601,15 +603,19 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 // then its start value from the seed parts and the preceding wavefronts' totals, exchanged
 // through LDS.  kahan = 0 uses plain float32 sums instead.
 // ---------------------------------------------------------------------------------------
-// exchange rows 0..5 (seed, its compensation, strip total, its compensation, seed count,
-// strip count), then the NW zero flags of note_zeros
+// exchange rows 0..3 (seed part, its compensation, strip total, its compensation), then
+// the NW zero flags of note_zeros
 template <int NW>
-__host__ __device__ constexpr int slide_scratch_floats() { return 6 * NW * 64 + NW; }
+__host__ __device__ constexpr int slide_scratch_floats() { return 4 * NW * 64 + NW; }
 
-template <int ORIENT, int S, int NW, bool PHASE_B, bool COUNT>
-__device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, float* lds,
-                                           const TileGeom<ORIENT>& g,
-                                           const EpiPlan<ORIENT, S, NW>& plan) {
+// First half of a sliding tile: this wavefront's share of the seed (spans i with
+// i % NW == wv, in increasing i), the per-step changes d[s] of its strip and their
+// compensated prefix (value P, compensation C: true sum = P - C).  The seed share and the
+// strip total go to the exchange rows.
+template <int ORIENT, int S, int NW>
+__device__ __forceinline__ void slide_steps(const PhaseArgs& p, const float* lds,
+                                            const TileGeom<ORIENT>& g, float* xs,
+                                            float (&P)[S], float (&C)[S]) {
     const int lane = threadIdx.x & 63, wv = wave_id();
     const float* lane_lds = lds + g.lane_part(lane - p.lane_min);
     const int lb = wv * S - p.c_min;   // this wavefront's strip start
@@ -617,9 +623,7 @@ __device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, f
     const int st = g.bstep();
     const bool kahan = p.kahan != 0;
     const ConstSpanPtr spans = as_const(p.spans);
-    // this wavefront's share of the seed: spans i with i % NW == wv, in increasing i
     float seed = 0.f, seed_c = 0.f;
-    int seed_n = 0;  // non-zero inputs in this wavefront's share of the seed windows
     for (int i = wv; i < p.n_spans; i += NW) {
         const DevSpan sp = load_span(spans, i);
         const float* base = lane_lds + g.uni_part(sp.lane_off, lb0 + sp.c0);
@@ -627,19 +631,12 @@ __device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, f
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         int q = 0;
         for (; q + 4 <= len; q += 4) {
-            const float v0 = base[q * st], v1 = base[(q + 1) * st];
-            const float v2 = base[(q + 2) * st], v3 = base[(q + 3) * st];
-            p0 += v0;
-            p1 += v1;
-            p2 += v2;
-            p3 += v3;
-            if (COUNT) seed_n += (nz(v0) + nz(v1)) + (nz(v2) + nz(v3));
+            p0 += base[q * st];
+            p1 += base[(q + 1) * st];
+            p2 += base[(q + 2) * st];
+            p3 += base[(q + 3) * st];
         }
-        for (; q < len; ++q) {
-            const float v0 = base[q * st];
-            p0 += v0;
-            if (COUNT) seed_n += nz(v0);
-        }
+        for (; q < len; ++q) p0 += base[q * st];
         const float part = (p0 + p1) + (p2 + p3);
         if (kahan) kahan_add(seed, seed_c, sp.w0 * part);
         else seed = fmaf(sp.w0, part, seed);
@@ -650,9 +647,8 @@ __device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, f
     // the seed): it reads an in-tile neighbour instead and is cleared afterwards.
     constexpr int U = S <= 8 ? 2 : 1;
     float d[S];
-    int dn[S];  // change of the non-zero count
 #pragma unroll
-    for (int s = 0; s < S; ++s) { d[s] = 0.f; dn[s] = 0; }
+    for (int s = 0; s < S; ++s) d[s] = 0.f;
     const int z0 = wv == 0 ? 1 : 0;
     int i = 0;
     for (; i + U <= p.n_spans; i += U) {
@@ -673,10 +669,7 @@ __device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, f
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                d[s] = fmaf(sp[u].w0, din[u][s] - dout[u][s], d[s]);
-                if (COUNT) dn[s] += nz(din[u][s]) - nz(dout[u][s]);
-            }
+            for (int s = 0; s < S; ++s) d[s] = fmaf(sp[u].w0, din[u][s] - dout[u][s], d[s]);
     }
     for (; i < p.n_spans; ++i) {
         const DevSpan sp = load_span(spans, i);
@@ -686,37 +679,90 @@ __device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, f
         for (int s = 0; s < S; ++s) {
             const float vin = bin[s * st], vout = base[(s == 0 ? z0 - 1 : s - 1) * st];
             d[s] = fmaf(sp.w0, vin - vout, d[s]);
-            if (COUNT) dn[s] += nz(vin) - nz(vout);
         }
     }
-    if (z0) { d[0] = 0.f; dn[0] = 0; }
-    // prefix of the changes inside the strip (value P, compensation C: true sum = P - C)
-    float P[S], C[S];
-    int Pn[S];
+    if (z0) d[0] = 0.f;
     {
         float run = 0.f, c = 0.f;
-        int rn = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (kahan) kahan_add(run, c, d[s]);
             else run += d[s];
             P[s] = run;
             C[s] = c;
-            rn += dn[s];
-            Pn[s] = rn;
         }
     }
-    // exchange seed parts and strip totals (values and non-zero counts)
-    float* xs = lds + g.ny * g.pitch;
     xs[(0 * NW + wv) * 64 + lane] = seed;
     xs[(1 * NW + wv) * 64 + lane] = seed_c;
     xs[(2 * NW + wv) * 64 + lane] = P[S - 1];
     xs[(3 * NW + wv) * 64 + lane] = C[S - 1];
-    if (COUNT) {
-        xs[(4 * NW + wv) * 64 + lane] = __int_as_float(seed_n);
-        xs[(5 * NW + wv) * 64 + lane] = __int_as_float(Pn[S - 1]);
+}
+
+// Non-zero inputs in the windows of this wavefront's S outputs: the first window counted
+// directly, then the changes of each step (entering minus leaving inputs of every span).
+// Only wavefronts that may hold an all-zero window run it.
+template <int ORIENT, int S>
+__device__ __forceinline__ void slide_counts(const PhaseArgs& p, const float* lds,
+                                             const TileGeom<ORIENT>& g, int (&n)[S]) {
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    const float* lane_lds = lds + g.lane_part(lane - p.lane_min);
+    const int lb = wv * S - p.c_min;
+    const int st = g.bstep();
+    const ConstSpanPtr spans = as_const(p.spans);
+#pragma unroll
+    for (int s = 0; s < S; ++s) n[s] = 0;
+#pragma unroll 1
+    for (int i = 0; i < p.n_spans; ++i) {
+        const DevSpan sp = load_span(spans, i);
+        const float* base = lane_lds + g.uni_part(sp.lane_off, lb + sp.c0);
+#pragma unroll 1
+        for (int q = 0; q < sp.len; ++q) n[0] += nz(base[q * st]);
+        const float* bin = base + (sp.len - 1) * st;
+#pragma unroll
+        for (int s = 1; s < S; ++s) n[s] += nz(bin[s * st]) - nz(base[(s - 1) * st]);
     }
+#pragma unroll
+    for (int s = 1; s < S; ++s) n[s] += n[s - 1];
+}
+
+template <int ORIENT, int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
+    constexpr int TA = 64, TB = NW * S;
+    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
+    EpiPlan<ORIENT, S, NW> plan;
+    epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
+    load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
+    lds_dma_wait();
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    float* xs = lds + g.ny * g.pitch;
+    int* zf = reinterpret_cast<int*>(xs + 4 * NW * 64);
+    // Exact zeros: does this wavefront need the non-zero counts?  With a span at least S
+    // long (p.wit), its columns S - 1 .. len - 1 lie in all S windows of a lane's strip: a
+    // non-zero input among four of them proves that none of the lane's windows is
+    // all-zero, so the counts are kept only if some lane of the wavefront finds none (an
+    // all-zero region, or zeros at all four places).  Without such a span, they are kept
+    // in tiles that hold a zero.  Counting wavefronts count their first window directly,
+    // so the decision need not be the same for the whole workgroup.
+    if (p.wit < 0) note_zeros(lds, g.ny, g.nx, g.pitch, zf);
     __syncthreads();
+    bool cnt;
+    if (p.wit >= 0) {
+        const DevSpan sw = load_span(as_const(p.spans), p.wit);
+        const float* wb = lds + g.lane_part(lane - p.lane_min) +
+                          g.uni_part(sw.lane_off, wv * S - p.c_min + sw.c0);
+        const int st = g.bstep(), spread = sw.len - S;
+        float m = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) m = fmaxf(m, fabsf(wb[(S - 1 + (spread * t) / 3) * st]));
+        cnt = __ballot(!(m > 0.f)) != 0ull;
+    } else {
+        cnt = tile_zeros<NW>(zf);
+    }
+    float P[S], C[S];
+    slide_steps<ORIENT, S, NW>(p, lds, g, xs, P, C);
+    __syncthreads();
+    // start value: the seed parts, then the strip totals of the preceding wavefronts
+    const bool kahan = p.kahan != 0;
     float base = 0.f, bc = 0.f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -732,35 +778,18 @@ __device__ __forceinline__ void slide_body(const PhaseArgs& p, int a0, int b0, f
             else base += part;
         }
     }
-    int base_n = 0;
-    if (COUNT) {
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            base_n += __float_as_int(xs[(4 * NW + w) * 64 + lane]);
-            if (w < wv) base_n += __float_as_int(xs[(5 * NW + w) * 64 + lane]);
-        }
-    }
     const float b_true = base - bc;
     float out[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-        out[s] = (COUNT && base_n + Pn[s] == 0) ? 0.f : b_true + (P[s] - C[s]);
+    for (int s = 0; s < S; ++s) out[s] = b_true + (P[s] - C[s]);
+    if (cnt) {  // the tile is intact until write_outputs' first barrier
+        int n[S];
+        slide_counts<ORIENT, S>(p, lds, g, n);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (n[s] == 0) out[s] = 0.f;
+    }
     write_outputs<ORIENT, S, NW, PHASE_B>(p, lds, a0, b0, out, plan);
-}
-
-template <int ORIENT, int S, int NW, bool PHASE_B>
-__device__ __forceinline__ void slide_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
-    constexpr int TA = 64, TB = NW * S;
-    TileGeom<ORIENT> g = make_geom<ORIENT>(p, a0, b0, TA, TB, 0);
-    EpiPlan<ORIENT, S, NW> plan;
-    epi_prefetch<ORIENT, S, NW, PHASE_B>(p, a0, b0, plan);
-    load_tile(lds, p.src, p.H, p.W, p.bc, g.ly0, g.lx0, g.ny, g.nx, g.pitch);
-    lds_dma_wait();
-    int* zf = reinterpret_cast<int*>(lds + g.ny * g.pitch + 6 * NW * 64);
-    note_zeros(lds, g.ny, g.nx, g.pitch, zf);
-    __syncthreads();
-    if (tile_zeros<NW>(zf)) slide_body<ORIENT, S, NW, PHASE_B, true>(p, a0, b0, lds, g, plan);
-    else slide_body<ORIENT, S, NW, PHASE_B, false>(p, a0, b0, lds, g, plan);
 }
 
 template <int ORIENT, int S, int NW, bool PHASE_B>
@@ -1465,38 +1494,39 @@ __device__ __forceinline__ void line_store(float* line, int pos, int n, int halo
 // p0 + c0 + q + len) for output q), seed by a direct sum, slide Kahan-compensated.
 // Exact zeros: every input is >= 0, so a direct float sum is 0 iff all of its terms are,
 // but a slid sum is not.  The inputs at [lo + SEG - 1, lo + len) lie in all SEG windows,
-// and the seed sums them separately: if that sum is positive no window is all-zero and the
-// slide stands.  Otherwise (rare) the non-zero inputs are counted exactly along the slide
-// and windows without any are set to 0.
-template <int SEG>
-__device__ __forceinline__ float box_range_sum(const float* line, int halo, int lo, int q0, int q1) {
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    int q = q0;
-#pragma unroll 1
-    for (; q + 4 <= q1; q += 4) {
-        s0 += line[line_idx<SEG>(lo + q, halo)];
-        s1 += line[line_idx<SEG>(lo + q + 1, halo)];
-        s2 += line[line_idx<SEG>(lo + q + 2, halo)];
-        s3 += line[line_idx<SEG>(lo + q + 3, halo)];
-    }
-    for (; q < q1; ++q) s0 += line[line_idx<SEG>(lo + q, halo)];
-    return (s0 + s1) + (s2 + s3);
-}
-
+// and a non-zero input among four of them proves that no window is all-zero, so the slide
+// stands.  Otherwise (rare) the non-zero inputs are counted exactly along the slide and
+// windows without any are set to 0.
 template <int SEG>
 __device__ __forceinline__ void box_segment(const float* line, int halo, int p0, int c0,
                                             int len, bool kahan, float (&out)[SEG]) {
     const int lo = p0 + c0;
     const int nh = min(SEG - 1, len);
-    const float head = box_range_sum<SEG>(line, halo, lo, 0, nh);
-    const float common = box_range_sum<SEG>(line, halo, lo, nh, len);
+    auto at = [&](int q) { return line[line_idx<SEG>(lo + q, halo)]; };
+    // seed: four partial sums over [0, len)
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int q = 0;
+#pragma unroll 1
+    for (; q + 4 <= len; q += 4) {
+        s0 += at(q);
+        s1 += at(q + 1);
+        s2 += at(q + 2);
+        s3 += at(q + 3);
+    }
+    for (; q < len; ++q) s0 += at(q);
+    // witness: four of the inputs at [nh, len), which every window of the segment holds
+    float m = 0.f;
+    if (len >= SEG) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) m = fmaxf(m, fabsf(at(nh + ((len - 1 - nh) * t) / 3)));
+    }
     float din[SEG], dout[SEG];
 #pragma unroll
     for (int q2 = 1; q2 < SEG; ++q2) {
-        din[q2] = line[line_idx<SEG>(lo + q2 + len - 1, halo)];
-        dout[q2] = line[line_idx<SEG>(lo + q2 - 1, halo)];
+        din[q2] = at(q2 + len - 1);
+        dout[q2] = at(q2 - 1);
     }
-    float run = head + common, c = 0.f;
+    float run = (s0 + s1) + (s2 + s3), c = 0.f;
     out[0] = run;
 #pragma unroll
     for (int q2 = 1; q2 < SEG; ++q2) {
@@ -1505,15 +1535,14 @@ __device__ __forceinline__ void box_segment(const float* line, int halo, int p0,
         else run += d;
         out[q2] = run;
     }
-    if (!(len >= SEG && common > 0.f)) {
+    if (!(m > 0.f)) {
         int n = 0;  // non-zero inputs in the window
 #pragma unroll 1
-        for (int t = 0; t < len; ++t) n += nz(line[line_idx<SEG>(lo + t, halo)]);
+        for (int t = 0; t < len; ++t) n += nz(at(t));
         if (n == 0) out[0] = 0.f;
 #pragma unroll
         for (int q2 = 1; q2 < SEG; ++q2) {
-            n += nz(line[line_idx<SEG>(lo + q2 + len - 1, halo)]) -
-                 nz(line[line_idx<SEG>(lo + q2 - 1, halo)]);
+            n += nz(at(q2 + len - 1)) - nz(at(q2 - 1));
             if (n == 0) out[q2] = 0.f;
         }
     }
