@@ -822,113 +822,29 @@ __device__ __forceinline__ void rl_add(float& s, float& c, float x, bool kahan) 
 }
 
 // LDS after the tile: ny rows of TB horizontal window sums (pitch TB + 1), then the NW
-// zero flags of note_zeros.  Exact zeros (tiles holding a zero only): the horizontal pass
-// counts the non-zero inputs of each window and stores exactly 0 for windows without any,
-// so a vertical window is all-zero iff all its horizontal sums are 0, which the vertical
-// pass counts the same way.
+// zero flags of note_zeros.
 template <int NW>
 __host__ __device__ constexpr size_t rect_lds_floats(int ny, int nx, int TB) {
     return (size_t)ny * (nx | 1) + (size_t)ny * rect_hs_pitch<NW>(TB) + NW;
 }
 
-template <int S, int NW, bool PHASE_B, bool COUNT>
-__device__ __forceinline__ void rect_body(const PhaseArgs& p, int a0, int b0, float* lds,
-                                          const EpiIn (&in)[RECT_SEG]) {
-    constexpr int TB = NW * S;
-    constexpr int NSEG_H = TB / RECT_SEG;       // horizontal segments per tile row
-    constexpr int NV = TB * (64 / RECT_SEG);    // vertical tasks (column, row segment)
-    const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
-    const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
-    float* hs = lds + ny * pitch;
-    const int tid = threadIdx.x;
-    const bool kahan = p.kahan != 0;
-    const int vb = tid % TB, vr = tid / TB;
-    const bool has_v = tid < NV;
-    // horizontal pass
-    for (int task = tid; task < ny * NSEG_H; task += NW * 64) {
-        const int r = task / NSEG_H, c0 = (task % NSEG_H) * RECT_SEG;
-        const float* row = lds + r * pitch + c0;
-        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-        int n = 0;
-        int t = 0;
-        for (; t + 4 <= kw; t += 4) {
-            q0 += row[t];
-            q1 += row[t + 1];
-            q2 += row[t + 2];
-            q3 += row[t + 3];
-            if (COUNT) n += (nz(row[t]) + nz(row[t + 1])) + (nz(row[t + 2]) + nz(row[t + 3]));
-        }
-        for (; t < kw; ++t) {
-            q0 += row[t];
-            if (COUNT) n += nz(row[t]);
-        }
-        float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
-        float* out = hs + r * rect_hs_pitch<NW>(TB) + c0;
-        out[0] = (!COUNT || n) ? sum : 0.f;
-#pragma unroll
-        for (int j = 1; j < RECT_SEG; ++j) {
-            rl_add(sum, comp, row[j + kw - 1] - row[j - 1], kahan);
-            if (COUNT) n += nz(row[j + kw - 1]) - nz(row[j - 1]);
-            out[j] = (!COUNT || n) ? sum - comp : 0.f;
-        }
-    }
-    __syncthreads();
-    // vertical pass and epilogue
-    int n_active = 0;
-    const float w = as_const(p.spans)[0].w0;
-    float v[RECT_SEG];
-    if (has_v) {
-        const int hp = rect_hs_pitch<NW>(TB);
-        const float* col = hs + (vr * RECT_SEG) * hp + vb;
-        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-        int n = 0;
-        int i = 0;
-        for (; i + 4 <= kh; i += 4) {
-            const float h0 = col[i * hp], h1 = col[(i + 1) * hp];
-            const float h2 = col[(i + 2) * hp], h3 = col[(i + 3) * hp];
-            q0 += h0;
-            q1 += h1;
-            q2 += h2;
-            q3 += h3;
-            if (COUNT) n += (nz(h0) + nz(h1)) + (nz(h2) + nz(h3));
-        }
-        for (; i < kh; ++i) {
-            q0 += col[i * hp];
-            if (COUNT) n += nz(col[i * hp]);
-        }
-        float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
-        v[0] = (!COUNT || n) ? sum : 0.f;
-#pragma unroll
-        for (int j = 1; j < RECT_SEG; ++j) {
-            const float hin = col[(j + kh - 1) * hp], hout = col[(j - 1) * hp];
-            rl_add(sum, comp, hin - hout, kahan);
-            if (COUNT) n += nz(hin) - nz(hout);
-            v[j] = (!COUNT || n) ? sum - comp : 0.f;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < RECT_SEG; ++j) {
-        int act = 0;
-        const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
-        if (has_v && y < p.H && x < p.W)
-            act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, in[j], w * v[j]);
-        if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
-    }
-    if (PHASE_B) add_active(p, n_active);
-}
-
 template <int S, int NW, bool PHASE_B>
 __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
     constexpr int TB = NW * S;
+    constexpr int NSEG_H = TB / RECT_SEG;       // horizontal segments per tile row
     constexpr int NV = TB * (64 / RECT_SEG);    // vertical tasks (column, row segment)
     static_assert(NV <= NW * 64, "one vertical task per thread");
     const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
     const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
+    const int hp = rect_hs_pitch<NW>(TB);
+    float* hs = lds + ny * pitch;  // ny rows of TB horizontal sums
     const int tid = threadIdx.x;
+    const bool kahan = p.kahan != 0;
     // vertical task of this thread and its outputs' epilogue inputs (loaded up front)
     const int vb = tid % TB, vr = tid / TB;
+    const bool has_v = tid < NV;
     EpiIn in[RECT_SEG];
-    if (tid < NV) {
+    if (has_v) {
 #pragma unroll
         for (int j = 0; j < RECT_SEG; ++j) {
             const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
@@ -940,8 +856,96 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
     int* zf = reinterpret_cast<int*>(lds + rect_lds_floats<NW>(ny, nx, TB) - NW);
     note_zeros(lds, ny, nx, pitch, zf);
     __syncthreads();
-    if (tile_zeros<NW>(zf)) rect_body<S, NW, PHASE_B, true>(p, a0, b0, lds, in);
-    else rect_body<S, NW, PHASE_B, false>(p, a0, b0, lds, in);
+    const bool cnt = tile_zeros<NW>(zf);  // the same for the whole workgroup
+    // horizontal pass
+    for (int task = tid; task < ny * NSEG_H; task += NW * 64) {
+        const int r = task / NSEG_H, c0 = (task % NSEG_H) * RECT_SEG;
+        const float* row = lds + r * pitch + c0;
+        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        int t = 0;
+        for (; t + 4 <= kw; t += 4) {
+            q0 += row[t];
+            q1 += row[t + 1];
+            q2 += row[t + 2];
+            q3 += row[t + 3];
+        }
+        for (; t < kw; ++t) q0 += row[t];
+        float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
+        float* out = hs + r * hp + c0;
+        out[0] = sum;
+#pragma unroll
+        for (int j = 1; j < RECT_SEG; ++j) {
+            rl_add(sum, comp, row[j + kw - 1] - row[j - 1], kahan);
+            out[j] = sum - comp;
+        }
+    }
+    __syncthreads();
+    // vertical pass
+    float v[RECT_SEG];
+    if (has_v) {
+        const float* col = hs + (vr * RECT_SEG) * hp + vb;
+        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        int i = 0;
+        for (; i + 4 <= kh; i += 4) {
+            q0 += col[i * hp];
+            q1 += col[(i + 1) * hp];
+            q2 += col[(i + 2) * hp];
+            q3 += col[(i + 3) * hp];
+        }
+        for (; i < kh; ++i) q0 += col[i * hp];
+        float sum = (q0 + q1) + (q2 + q3), comp = 0.f;
+        v[0] = sum;
+#pragma unroll
+        for (int j = 1; j < RECT_SEG; ++j) {
+            rl_add(sum, comp, col[(j + kh - 1) * hp] - col[(j - 1) * hp], kahan);
+            v[j] = sum - comp;
+        }
+    }
+    // Exact zeros (tiles holding a zero): the same two passes over non-zero counts, the
+    // horizontal ones in place of the sums, and windows with none give exactly 0.
+    if (cnt) {
+        int* hn = reinterpret_cast<int*>(hs);
+        __syncthreads();  // everyone is done reading the sums
+        for (int task = tid; task < ny * NSEG_H; task += NW * 64) {
+            const int r = task / NSEG_H, c0 = (task % NSEG_H) * RECT_SEG;
+            const float* row = lds + r * pitch + c0;
+            int n = 0;
+#pragma unroll 1
+            for (int t = 0; t < kw; ++t) n += nz(row[t]);
+            int* outn = hn + r * hp + c0;
+            outn[0] = n;
+#pragma unroll
+            for (int j = 1; j < RECT_SEG; ++j) {
+                n += nz(row[j + kw - 1]) - nz(row[j - 1]);
+                outn[j] = n;
+            }
+        }
+        __syncthreads();
+        if (has_v) {
+            const int* coln = hn + (vr * RECT_SEG) * hp + vb;
+            int n = 0;
+#pragma unroll 1
+            for (int i = 0; i < kh; ++i) n += coln[i * hp];
+            if (n == 0) v[0] = 0.f;
+#pragma unroll
+            for (int j = 1; j < RECT_SEG; ++j) {
+                n += coln[(j + kh - 1) * hp] - coln[(j - 1) * hp];
+                if (n == 0) v[j] = 0.f;
+            }
+        }
+    }
+    // epilogue
+    int n_active = 0;
+    const float w = as_const(p.spans)[0].w0;
+#pragma unroll
+    for (int j = 0; j < RECT_SEG; ++j) {
+        int act = 0;
+        const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
+        if (has_v && y < p.H && x < p.W)
+            act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, in[j], w * v[j]);
+        if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+    }
+    if (PHASE_B) add_active(p, n_active);
 }
 
 template <int S, int NW, bool PHASE_B>
@@ -960,11 +964,11 @@ __global__ __launch_bounds__(NW * 64) void rect_kernel(LaunchArgs L) {
 // -- but with T built per tile in LDS instead of over the whole image: the tile's rows are
 // prefix-summed (one thread per row), then its columns (one thread per column).  T is held
 // in FP64: its entries grow with the tile's total, and a float32 table would lose the small
-// windows to cancellation.  Exact zeros (tiles holding a zero only): the row pass also
-// overwrites each tile value with the running count of non-zero values of its row (the
-// value itself is not needed afterwards), the column pass turns those into 2-D counts, and
-// windows with a zero count give exactly 0.  Work per output is constant in kh and kw:
-// four corner reads and three FP64 adds.
+// windows to cancellation.  Exact zeros (tiles holding a zero only): after the FP64 row
+// pass, a count pass overwrites each tile value with the running count of non-zero values
+// of its row (the values are not needed any more), a column pass turns those into 2-D
+// counts, and windows with a zero count give exactly 0.  Work per output is constant in kh
+// and kw: four corner reads and three FP64 adds.
 // ---------------------------------------------------------------------------------------
 __host__ __device__ constexpr int sat_pitch(int nx) { return (nx + 1) | 1; }
 
@@ -978,25 +982,39 @@ __host__ __device__ constexpr size_t sat_lds_bytes(int ny, int nx) {
     return sat_table_offset(ny, nx) + (size_t)(ny + 1) * sat_pitch(nx) * 8 + NW * 4;
 }
 
-template <int S, int NW, bool PHASE_B, bool COUNT>
-__device__ __forceinline__ void sat_body(const PhaseArgs& p, int a0, int b0, float* lds,
-                                         const EpiIn (&in)[RECT_SEG]) {
+template <int S, int NW, bool PHASE_B>
+__device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
     constexpr int TB = NW * S;
     constexpr int NV = TB * (64 / RECT_SEG);
+    static_assert(NV <= NW * 64, "one output task per thread");
     const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
     const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1, tp = sat_pitch(nx);
     double* T = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + sat_table_offset(ny, nx));
     int* N = reinterpret_cast<int*>(lds);  // inclusive counts, in place of the tile
     const int tid = threadIdx.x;
+    const int vb = tid % TB, vr = tid / TB;
+    const bool has_v = tid < NV;
+    EpiIn in[RECT_SEG];
+    if (has_v) {
+#pragma unroll
+        for (int j = 0; j < RECT_SEG; ++j) {
+            const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
+            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+        }
+    }
+    load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
+    lds_dma_wait();
+    int* zf = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + sat_lds_bytes<NW>(ny, nx)) - NW;
+    note_zeros(lds, ny, nx, pitch, zf);
+    __syncthreads();
+    const bool cnt = tile_zeros<NW>(zf);  // the same for the whole workgroup
     // row 0 of T is 0; each row's prefix starts at column 0 = 0
     for (int j = tid; j <= nx; j += NW * 64) T[j] = 0.0;
     // row prefix sums: T(i + 1, j + 1) = sum of tile row i, columns 0..j
     for (int i = tid; i < ny; i += NW * 64) {
         const float* row = lds + i * pitch;
-        int* nrow = N + i * pitch;
         double* trow = T + (size_t)(i + 1) * tp;
         double s = 0.0;
-        int n = 0;
         trow[0] = 0.0;
         int j = 0;
         for (; j + 4 <= nx; j += 4) {
@@ -1009,30 +1027,14 @@ __device__ __forceinline__ void sat_body(const PhaseArgs& p, int a0, int b0, flo
             trow[j + 3] = s;
             s += (double)v3;
             trow[j + 4] = s;
-            if (COUNT) {
-                n += nz(v0);
-                nrow[j] = n;
-                n += nz(v1);
-                nrow[j + 1] = n;
-                n += nz(v2);
-                nrow[j + 2] = n;
-                n += nz(v3);
-                nrow[j + 3] = n;
-            }
         }
         for (; j < nx; ++j) {
-            const float v = row[j];
-            s += (double)v;
+            s += (double)row[j];
             trow[j + 1] = s;
-            if (COUNT) {
-                n += nz(v);
-                nrow[j] = n;
-            }
         }
     }
     __syncthreads();
-    // column prefix sums: T(i, j) becomes the sum over tile rows < i and columns < j;
-    // N(i, j) the count over tile rows <= i and columns <= j
+    // column prefix sums: T(i, j) becomes the sum over tile rows < i and columns < j
     for (int j = 1 + tid; j <= nx; j += NW * 64) {
         double s = 0.0;
         int i = 1;
@@ -1052,19 +1054,32 @@ __device__ __forceinline__ void sat_body(const PhaseArgs& p, int a0, int b0, flo
             s += T[(size_t)i * tp + j];
             T[(size_t)i * tp + j] = s;
         }
-        if (COUNT) {
-            int* c = N + (j - 1);
+    }
+    if (cnt) {
+        // row prefixes of the non-zero counts, each overwriting its own tile row (the
+        // values are not needed any more): N(i, j) counts row i, columns 0..j
+        for (int i = tid; i < ny; i += NW * 64) {
+            float* row = lds + i * pitch;
             int n = 0;
+#pragma unroll 1
+            for (int j = 0; j < nx; ++j) {
+                n += nz(row[j]);
+                reinterpret_cast<int*>(row)[j] = n;
+            }
+        }
+        __syncthreads();
+        // column prefixes: N(i, j) counts rows 0..i, columns 0..j
+        for (int j = tid; j < nx; j += NW * 64) {
+            int n = 0;
+#pragma unroll 1
             for (int r = 0; r < ny; ++r) {
-                n += c[r * pitch];
-                c[r * pitch] = n;
+                n += N[r * pitch + j];
+                N[r * pitch + j] = n;
             }
         }
     }
     __syncthreads();
     // outputs from four corners: thread task (column vb, rows vr*8 .. vr*8+7)
-    const int vb = tid % TB, vr = tid / TB;
-    const bool has_v = tid < NV;
     const float w = as_const(p.spans)[0].w0;
     auto cnt_at = [&](int i, int j) { return (i < 0 || j < 0) ? 0 : N[i * pitch + j]; };
     int n_active = 0;
@@ -1077,7 +1092,7 @@ __device__ __forceinline__ void sat_body(const PhaseArgs& p, int a0, int b0, flo
             const size_t r0 = (size_t)a * tp, r1 = (size_t)(a + kh) * tp;
             const double sum = (T[r1 + vb + kw] - T[r0 + vb + kw]) - (T[r1 + vb] - T[r0 + vb]);
             float v = (float)sum;
-            if (COUNT) {
+            if (cnt) {
                 const int n = (cnt_at(a + kh - 1, vb + kw - 1) - cnt_at(a - 1, vb + kw - 1)) -
                               (cnt_at(a + kh - 1, vb - 1) - cnt_at(a - 1, vb - 1));
                 if (n == 0) v = 0.f;
@@ -1087,32 +1102,6 @@ __device__ __forceinline__ void sat_body(const PhaseArgs& p, int a0, int b0, flo
         if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
     }
     if (PHASE_B) add_active(p, n_active);
-}
-
-template <int S, int NW, bool PHASE_B>
-__device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
-    constexpr int TB = NW * S;
-    constexpr int NV = TB * (64 / RECT_SEG);
-    static_assert(NV <= NW * 64, "one output task per thread");
-    const int kh = p.lane_max - p.lane_min + 1, kw = p.c_max - p.c_min + 1;
-    const int ny = 64 + kh - 1, nx = TB + kw - 1, pitch = nx | 1;
-    const int tid = threadIdx.x;
-    const int vb = tid % TB, vr = tid / TB;
-    EpiIn in[RECT_SEG];
-    if (tid < NV) {
-#pragma unroll
-        for (int j = 0; j < RECT_SEG; ++j) {
-            const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
-            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
-        }
-    }
-    load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
-    lds_dma_wait();
-    int* zf = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + sat_lds_bytes<NW>(ny, nx)) - NW;
-    note_zeros(lds, ny, nx, pitch, zf);
-    __syncthreads();
-    if (tile_zeros<NW>(zf)) sat_body<S, NW, PHASE_B, true>(p, a0, b0, lds, in);
-    else sat_body<S, NW, PHASE_B, false>(p, a0, b0, lds, in);
 }
 
 template <int S, int NW, bool PHASE_B>
