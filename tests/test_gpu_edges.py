@@ -110,3 +110,46 @@ def test_constant_image_is_fixed_point():
         u, _ = run_gpu(f, h, 10)
         # every path sums the normalised PSF to 1 within float32 rounding
         assert np.max(np.abs(u - 0.37)) <= 1e-5 * 0.37, h.shape
+
+
+SPARSE_CASES = [("disc5", lambda: synth.disc(5), [("runs", "auto"), ("direct", "auto")]),
+                ("box_h13", lambda: synth.box_h(13), [("box_axis", "two_pass"),
+                                                      ("box_axis", "resident")]),
+                ("box_v11", lambda: synth.box_v(11), [("box_axis", "two_pass"),
+                                                      ("box_axis", "resident")]),
+                ("rect6x9", lambda: synth.box_rect(6, 9), [("box_rect", "auto"),
+                                                           ("box_sat", "auto"), ("runs", "auto")])]
+
+
+@pytest.mark.parametrize("density", [0.5, 0.9])
+@pytest.mark.parametrize("name,mk,paths", SPARSE_CASES, ids=[c[0] for c in SPARSE_CASES])
+def test_sparse_zeros(orc, name, mk, paths, density):
+    """Inputs with many scattered exact zeros: the zero tests of the sliding kernels find
+    zeros almost everywhere, so most wavefronts take the counting path, and a few windows
+    are all-zero (density 0.9)."""
+    h = mk()
+    rng = np.random.default_rng(86)
+    f = _obs(96, 130, h, 86)
+    f[rng.random(f.shape) < density] = 0.0
+    ref = orc.rl(f, h, 5)
+    for path, sched in paths:
+        u, _ = run_gpu(f, h, 5, path=path, schedule=sched)
+        err = rel_err(u, ref)
+        print(f"{name} {density} {path}/{sched}: {err:.3g}")
+        assert err <= RTOL, (path, sched, err)
+        assert np.array_equal(u == 0.0, ref == 0.0), (path, sched)
+
+
+def test_all_zero_and_single_pixel(orc):
+    for h, paths in [(synth.disc(4), ["runs", "direct"]), (synth.box_h(9), ["box_axis"]),
+                     (synth.box_rect(3, 5), ["box_rect", "box_sat"])]:
+        f = np.zeros((70, 75), np.float32)
+        for path in paths:
+            u, _ = run_gpu(f, h, 3, path=path)
+            assert np.all(u == 0.0), path
+        f[30, 40] = 1.0
+        ref = orc.rl(f, h, 4)
+        for path in paths:
+            u, _ = run_gpu(f, h, 4, path=path)
+            assert rel_err(u, ref) <= RTOL, path
+            assert np.array_equal(u == 0.0, ref == 0.0), path
