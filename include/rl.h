@@ -173,7 +173,9 @@ rl_status rl_workspace_bytes(const rl_params *p, size_t *bytes);
 rl_status rl_init(const rl_params *p, void *ws, size_t ws_bytes, rl_job **out);
 
 /* Enqueue n_iter >= 0 further RL iterations (Section 2, eq. 3; thinned per Section 4 when
- * p->thin.mode != RL_THIN_OFF).  Asynchronous. */
+ * p->thin.mode != RL_THIN_OFF).  Asynchronous.  Every path returns exactly 0 for a window
+ * whose inputs are all 0 (so r = 0 where v = 0, and u^{k+1} = 0 where c = 0), also the
+ * sliding ones, which count the non-zero inputs of such windows exactly. */
 rl_status rl_iterate(rl_job *job, int32_t n_iter);
 
 /*
