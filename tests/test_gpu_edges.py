@@ -153,3 +153,22 @@ def test_all_zero_and_single_pixel(orc):
             u, _ = run_gpu(f, h, 4, path=path)
             assert rel_err(u, ref) <= RTOL, path
             assert np.array_equal(u == 0.0, ref == 0.0), path
+
+
+@pytest.mark.parametrize("strip", [4, 8, 16, 32])
+def test_zero_witness_across_strips(orc, strip):
+    """The sliding kernel's witness needs a run at least one strip long: with a 31-wide
+    box every strip width has one, with a disc of radius 5 (runs of at most 11) the wide
+    strips fall back to the tile scan.  Both decisions must give the oracle's zeros."""
+    rng = np.random.default_rng(87)
+    for h in (synth.box_h(31), synth.disc(5)):
+        f = _obs(100, 180, h, 87)
+        f[20:60, 30:120] = 0.0
+        f[rng.random(f.shape) < 0.3] = 0.0
+        ref = orc.rl(f, h, 5)
+        path = "box_axis" if h.shape[0] == 1 else "runs"
+        sched = "two_pass" if path == "box_axis" else "auto"
+        u, info = run_gpu(f, h, 5, path=path, schedule=sched, tuning=dict(strip=strip))
+        assert info["strip"] == strip
+        assert rel_err(u, ref) <= RTOL, (h.shape, strip)
+        assert np.array_equal(u == 0.0, ref == 0.0), (h.shape, strip)
