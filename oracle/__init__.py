@@ -84,6 +84,16 @@ def _load(mutant=0):
         lib.oracle_rl_tv.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, dp, dp]
+        lib.oracle_idiv.restype = ctypes.c_double
+        lib.oracle_idiv.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.oracle_rl_robust.restype = None
+        lib.oracle_rl_robust.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, dp, dp, dp, dp]
+        lib.oracle_robust_terms.restype = None
+        lib.oracle_robust_terms.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp,
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_double, dp, dp, dp, dp]
         lib.oracle_sum.restype = ctypes.c_double
         lib.oracle_sum.argtypes = [dp, ctypes.c_long]
         _libs[mutant] = lib
@@ -153,6 +163,33 @@ class Oracle:
                               BC[bc], int(K), float(lam), float(eps), r.ctypes.data_as(dp),
                               d.ctypes.data_as(dp))
         return u
+
+    def idiv(self, v, f):
+        """Pointwise I-divergence d(v, f) = v - f - f ln(v / f) of the robust variant."""
+        return float(self.lib.oracle_idiv(float(v), float(f)))
+
+    def rl_robust(self, f, h, K, eps, bc="reflect", u0=None):
+        """K iterations of RL with the robustified data term (weights 1/sqrt(d + eps^2) of
+        the I-divergence d) from u^0 = f (or ``u0``)."""
+        f, fp = self._d(f)
+        u, up = self._d(np.array(f if u0 is None else u0, dtype=np.float64, copy=True))
+        h, hp = self._d(h)
+        work = [np.empty_like(f) for _ in range(4)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.lib.oracle_rl_robust(fp, up, f.shape[0], f.shape[1], hp, h.shape[0], h.shape[1],
+                                  BC[bc], int(K), float(eps), *[a.ctypes.data_as(dp) for a in work])
+        return u
+
+    def robust_terms(self, f, u, h, eps, bc="reflect"):
+        """(num, den) of one robust iteration at u: h^* * (w f / v) and h^* * w."""
+        f, fp = self._d(f)
+        u, up = self._d(u)
+        h, hp = self._d(h)
+        work = [np.empty_like(f) for _ in range(4)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.lib.oracle_robust_terms(fp, up, f.shape[0], f.shape[1], hp, h.shape[0], h.shape[1],
+                                     BC[bc], float(eps), *[a.ctypes.data_as(dp) for a in work])
+        return work[2], work[3]
 
     def below(self, a, b, mode, tau):
         """float32 convergence decision of Section 4 (ABS or REL threshold)."""

@@ -16,6 +16,8 @@
  *     treatment").  Two readings are offered:
  *       BC_REFLECT   half-sample symmetric continuation (c b a | a b c), period 2N;
  *       BC_REPLICATE the closest image pixel (constant continuation), the paper's rule.
+ *   - robustified data term (Section 2 names such variants): weights 1/sqrt(d + eps^2) of
+ *     the I-divergence d of u^k*h from f, see oracle_rl_robust
  *   - thinned RL: active pixels get fresh v^k and u^{k+1}; inactive pixels keep v^{k-1}
  *     (here: keep their ratio r) and u^k; every R-th iteration all pixels are active
  *     (Section 4, eq. 4-5 and the reset rule after them).
@@ -231,6 +233,71 @@ void oracle_rl_tv(const double *f, double *u, int H, int W, const double *h, int
                 const double c = corr_at(r, H, W, h, kh, kw, bc, y, x);
                 u[y * W + x] = update(u[y * W + x], c) / (1.0 - lambda * div[y * W + x]);
             }
+    }
+}
+
+/*
+ * Robustified data term (Section 2 names robust variants among the methods the
+ * optimisations carry over to).  Reading: the multiplicative iteration of a robust
+ * penaliser Phi applied to the pointwise I-divergence of the blurred estimate v = u*h
+ * from f,
+ *   d(v, f) = v - f - f ln(v / f)   (d = v where f = 0),
+ * with Phi(d) = 2 sqrt(d + eps^2), i.e. weights w = Phi'(d) = 1 / sqrt(d + eps^2):
+ *   u^{k+1} = u^k . (h^* * (w f / v)) / (h^* * w).
+ * Where v <= 0 the ratio is 0 (as in plain RL) and d is taken as 0.  A constant w (eps
+ * large) gives plain RL.
+ */
+double oracle_idiv(double v, double f)
+{
+    if (!(v > 0.0)) return 0.0;
+    if (f == 0.0) return v;
+#if ORACLE_MUTANT == 9
+    return v - f + f * log(v / f); /* planted: sign of the log term */
+#else
+    return v - f - f * log(v / f);
+#endif
+}
+
+static double robust_weight(double d, double eps)
+{
+#if ORACLE_MUTANT == 8
+    return 1.0 / (d + eps * eps); /* planted: weight without the square root */
+#else
+    return 1.0 / sqrt(d + eps * eps);
+#endif
+}
+
+/* The two correlations of one robust iteration at u: num = h^* * (w f / v), den = h^* * w;
+ * r and w are work arrays (they receive w f / v and w). */
+void oracle_robust_terms(const double *f, const double *u, int H, int W, const double *h,
+                         int kh, int kw, int bc, double eps, double *r, double *w, double *num,
+                         double *den)
+{
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            const double v = conv_at(u, H, W, h, kh, kw, bc, y, x);
+            const double fw = f[y * W + x];
+            const double wt = robust_weight(oracle_idiv(v, fw), eps);
+            w[y * W + x] = wt;
+            r[y * W + x] = wt * ratio(fw, v);
+        }
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            num[y * W + x] = corr_at(r, H, W, h, kh, kw, bc, y, x);
+            den[y * W + x] = corr_at(w, H, W, h, kh, kw, bc, y, x);
+        }
+}
+
+/* K robust iterations from u (in/out); r, w, num, den are work arrays. */
+void oracle_rl_robust(const double *f, double *u, int H, int W, const double *h, int kh, int kw,
+                      int bc, int K, double eps, double *r, double *w, double *num, double *den)
+{
+    for (int k = 0; k < K; ++k) {
+        oracle_robust_terms(f, u, H, W, h, kh, kw, bc, eps, r, w, num, den);
+        /* every term of den is positive: den > 0 wherever the PSF is non-empty */
+        for (long q = 0; q < (long)H * W; ++q) u[q] = update(u[q], num[q]) / den[q];
     }
 }
 

@@ -307,6 +307,22 @@ def _pins_pass(o):
             f = ndimage.convolve(u, h64, mode="reflect")
             if not np.allclose(o.rl(f, h64, 3, u0=u), u * h64.sum(), rtol=1e-12):
                 return False
+        # robust variant: weights against the gradient of its energy (scipy rel_entr)
+        from scipy.special import rel_entr
+        h = _unit(synth.disc(2))
+        f = ndimage.convolve(u, h, mode="reflect") * RNG.uniform(0.7, 1.3, u.shape)
+        uu = RNG.uniform(0.2, 1.0, u.shape)
+
+        def energy(x):
+            v = ndimage.convolve(x, h, mode="reflect")
+            return float(np.sum(2.0 * np.sqrt(v - f + rel_entr(f, v) + 0.0025)))
+
+        num, den = o.robust_terms(f, uu, h, 0.05)
+        ep = np.zeros_like(uu)
+        ep[5, 6] = 1e-6
+        g = (energy(uu + ep) - energy(uu - ep)) / 2e-6
+        if not abs((den - num)[5, 6] - g) <= 1e-5 * max(1.0, abs(g)):
+            return False
         e = 2.0 ** -13
         if o.below(1.0 + e, 1.0, "abs", e) or not o.below(1.0 + e, 1.0, "abs", 1.5 * e):
             return False
@@ -319,7 +335,7 @@ def _pins_pass(o):
 
 def test_planted_mistakes_are_caught():
     assert _pins_pass(oracle.Oracle(0))
-    for m in range(1, 8):
+    for m in range(1, 10):
         assert not _pins_pass(oracle.Oracle(m)), f"mutant {m} passed the pins"
 
 
@@ -387,3 +403,71 @@ def test_tv_constant_fixed_point(orc):
     f = np.full((30, 26), 0.4)
     u = orc.rl_tv(f, h, 5, 0.1, 1e-3)
     assert np.allclose(u, f, rtol=0, atol=1e-15)
+
+
+# ---- robustified data term: I-divergence weights ---------------------------------------
+def test_robust_idiv_matches_rel_entr(orc):
+    """d(v, f) = v - f - f ln(v/f) is v - f + rel_entr(f, v) (scipy), also at f = 0."""
+    from scipy.special import rel_entr
+    v = RNG.uniform(1e-3, 3.0, 200)
+    f = np.concatenate([RNG.uniform(1e-3, 3.0, 150), np.zeros(50)])
+    for vi, fi in zip(v, f):
+        want = vi - fi + float(rel_entr(fi, vi))
+        assert abs(orc.idiv(vi, fi) - want) <= 1e-12 * max(1.0, abs(want))
+    assert orc.idiv(0.7, 0.7) == 0.0
+    assert orc.idiv(0.0, 0.5) == 0.0  # v <= 0: no information
+
+
+def _unit(h):
+    h = np.asarray(h, np.float64)
+    return h / h.sum()
+
+
+def test_robust_constant_weights_are_plain_rl(orc):
+    """eps far above every divergence: the weights are constant and cancel, so the update
+    is plain RL's (PSFs normalised in FP64: a sum off 1 would scale every step by it)."""
+    for h in [synth.disc(3), synth.oblique_line(9, 40.0), synth.box_rect(3, 5)]:
+        h = _unit(h)
+        f = synth.observe(synth.latent_image(40, 36, 8), h, "poisson", 8).astype(np.float64)
+        a = orc.rl_robust(f, h, 4, 1e8)
+        b = orc.rl(f, h, 4)
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-15)
+
+
+def test_robust_fixed_points(orc):
+    """Constant images, and the true image of noise-free data (f = g*h by scipy, u^0 = g):
+    d = 0 everywhere, constant weights, u^1 = u^0."""
+    h = _unit(synth.disc(3))
+    c = np.full((30, 34), 0.37)
+    np.testing.assert_allclose(orc.rl_robust(c, h, 3, 0.05), c, rtol=1e-13)
+    g = RNG.uniform(0.2, 1.0, (30, 34))
+    f = ndimage.convolve(g, h, mode="reflect")
+    np.testing.assert_allclose(orc.rl_robust(f, h, 1, 0.05, u0=g), g, rtol=1e-12)
+
+
+@pytest.mark.parametrize("psf,points", [
+    ("disc2", [(0, 0), (5, 7), (12, 21), (23, 3), (17, 17)]),       # mirror-symmetric: all
+    ("oblique7", [(6, 6), (10, 14), (15, 9)]),                      # interior only
+])
+def test_robust_gradient_identity(orc, psf, points):
+    """den - num is the gradient of E(u) = sum 2 sqrt(d(u*h, f) + eps^2), checked against
+    central differences of E computed with scipy (convolve, rel_entr).  The correlation is
+    the exact adjoint of the reflected convolution for mirror-symmetric PSFs everywhere,
+    for others away from the image edges."""
+    from scipy.special import rel_entr
+    h = _unit(synth.disc(2) if psf == "disc2" else synth.oblique_line(7, 30.0))
+    eps = 0.05
+    f = synth.observe(synth.latent_image(24, 22, 9), synth.disc(2), "poisson", 9).astype(np.float64)
+    u = RNG.uniform(0.1, 1.0, f.shape)
+
+    def energy(uu):
+        v = ndimage.convolve(uu, h, mode="reflect")
+        d = v - f + rel_entr(f, v)
+        return float(np.sum(2.0 * np.sqrt(d + eps * eps)))
+
+    num, den = orc.robust_terms(f, u, h, eps)
+    for (y, x) in points:
+        e = np.zeros_like(u)
+        e[y, x] = 1e-6
+        g = (energy(u + e) - energy(u - e)) / 2e-6
+        assert abs((den - num)[y, x] - g) <= 1e-5 * max(1.0, abs(g)), (y, x, (den - num)[y, x], g)
