@@ -135,6 +135,15 @@ typedef struct rl_params {
      * (RL_E_UNSUPPORTED).                                                                */
     float tv_lambda;
     float tv_eps;
+    /* Robustified data term (the paper names robust RL variants among the methods its
+     * optimisations carry over to, Section 2): rob_eps > 0 turns the update into
+     *   u^{k+1} = u^k . (h^* * (w f / v)) / (h^* * w),   v = u^k * h,
+     *   w = 1 / sqrt(d + rob_eps^2),  d = v - f - f ln(v / f)  (I-divergence; d = v where
+     *   f = 0; d = 0 and w f / v = 0 where v <= 0),
+     * i.e. a square-root penaliser of the I-divergence.  Each iteration runs the forward
+     * sum, an elementwise weight pass and two correlations.  rob_eps = 0 disables it; not
+     * combined with TV, thinning, the resident or the fused schedule (RL_E_UNSUPPORTED).  */
+    float rob_eps;
 } rl_params;
 
 typedef struct rl_stats {

@@ -52,7 +52,8 @@ class rl_params(ctypes.Structure):
                 ("boundary", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("kahan", ctypes.c_int32),
                 ("thin", rl_thin), ("stream", ctypes.c_void_p), ("tuning", rl_tuning),
-                ("tv_lambda", ctypes.c_float), ("tv_eps", ctypes.c_float)]
+                ("tv_lambda", ctypes.c_float), ("tv_eps", ctypes.c_float),
+                ("rob_eps", ctypes.c_float)]
 
 
 class rl_stats(ctypes.Structure):

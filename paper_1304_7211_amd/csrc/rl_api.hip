@@ -59,7 +59,7 @@ struct Config {
 
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
-        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, tvg,
+        bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, tvg, wt,
         total;
 };
 
@@ -196,6 +196,11 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         *why = "TV regularisation runs on the two-pass schedule without thinning";
         return RL_E_UNSUPPORTED;
     }
+    const bool rob = p->rob_eps > 0.f;
+    if (rob && (tv || thin || sched == RL_SCHED_FUSED || sched == RL_SCHED_RESIDENT)) {
+        *why = "the robust data term runs on the two-pass schedule, without TV or thinning";
+        return RL_E_UNSUPPORTED;
+    }
     if (sched == RL_SCHED_PERSISTENT) {
         // Switched off: its first GPU run did not finish, and no cause has been shown yet.
         *why = "the persistent schedule is switched off";
@@ -230,7 +235,8 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         return RL_OK;
     }
     const int box_orient = c.box_orient == rl::Orient::Rows ? rlk::ORIENT_ROWS : rlk::ORIENT_COLS;
-    if (path == RL_PATH_BOX_AXIS && !thin && !tv && (sched == RL_SCHED_AUTO || sched == RL_SCHED_RESIDENT)) {
+    if (path == RL_PATH_BOX_AXIS && !thin && !tv && !rob &&
+        (sched == RL_SCHED_AUTO || sched == RL_SCHED_RESIDENT)) {
         int n = box_orient == rlk::ORIENT_ROWS ? W : H;
         int m = box_orient == rlk::ORIENT_ROWS ? H : W;
         // the on-chip halo holds a single reflection: needs L - 1 <= line length
@@ -437,7 +443,9 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     L.red_i = take(rlk::RED_BLOCKS * 8);
     L.done = cfg.sched == RL_SCHED_PERSISTENT ? take(ntiles * 4) : 0;
     L.pctl = take(2 * sizeof(int32_t));  // persistent launches: ticket, abort flag
-    L.tvg = p->tv_lambda > 0.f ? take(N * 4) : 0;
+    const bool rob = p->rob_eps > 0.f;
+    L.tvg = (p->tv_lambda > 0.f || rob) ? take(N * 4) : 0;  // TV factor or robust h^* * w
+    L.wt = rob ? take(N * 4) : 0;                           // robust weights w
     L.total = o;
     return L;
 }
@@ -449,6 +457,7 @@ rl_status validate_params(const rl_params* p, std::string* why) {
     if (p->boundary != RL_BC_REFLECT && p->boundary != RL_BC_REPLICATE) { *why = "boundary"; return RL_E_INVAL; }
     if (!(p->tv_lambda >= 0.f && p->tv_lambda < 0.25f)) { *why = "tv_lambda in [0, 0.25)"; return RL_E_INVAL; }
     if (p->tv_lambda > 0.f && !(p->tv_eps > 0.f && p->tv_eps < 1e30f)) { *why = "tv_eps > 0"; return RL_E_INVAL; }
+    if (!(p->rob_eps >= 0.f && p->rob_eps < 1e18f)) { *why = "rob_eps >= 0 and finite"; return RL_E_INVAL; }
     if (p->thin.mode < RL_THIN_OFF || p->thin.mode > RL_THIN_REL) { *why = "thin mode"; return RL_E_INVAL; }
     if (p->thin.mode != RL_THIN_OFF) {
         if (!(p->thin.tau >= 0.f) || std::isinf(p->thin.tau)) { *why = "tau"; return RL_E_INVAL; }
@@ -716,7 +725,10 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     a.k = k0;
     a.full = 1;
     a.list_ok = 1;
-    a.tvg = (phase_b && j->p.tv_lambda > 0.f) ? j->at<float>(j->L.tvg) : nullptr;
+    // robust variant: phase A stores v (the r plane), phase B divides by h^* * w
+    a.tvg = (phase_b && (j->p.tv_lambda > 0.f || j->p.rob_eps > 0.f)) ? j->at<float>(j->L.tvg)
+                                                                      : nullptr;
+    a.store = (!phase_b && j->p.rob_eps > 0.f) ? j->at<float>(j->L.r) : nullptr;
     // the sliding kernel's exact-zero witness: the longest run, if it covers a strip
     a.wit = -1;
     if (c.kind == KIND_SLIDE) {
@@ -987,6 +999,23 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
         if (rl_status tst = enqueue_tv(j, s)) return tst;
         rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, la), na);
         if (st) return st;
+        if (j->p.rob_eps > 0.f) {
+            // robust variant: weights and weighted ratio from v, then h^* * w into the
+            // denominator plane, then the update's correlation
+            float* r = j->at<float>(j->L.r);
+            float* wt = j->at<float>(j->L.wt);
+            st = dev_err(launch("robust_weights", rlk::robust_weights_kernel,
+                                dim3(grid_for(j->N, 256, 4096)), dim3(256), 0, s, r,
+                                (const float*)j->at<float>(j->L.f), wt, (int64_t)j->N,
+                                j->p.rob_eps * j->p.rob_eps), "robust_weights");
+            if (st) return st;
+            rlk::LaunchArgs lw = lb;
+            lw.one.src = wt;
+            lw.one.store = j->at<float>(j->L.tvg);
+            lw.one.tvg = nullptr;
+            st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lw), nbn);
+            if (st) return st;
+        }
         st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lb), nbn);
         if (st) return st;
         j->k += 1;
@@ -1324,7 +1353,9 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     rl_status st;
     std::vector<int> tiled, resident;
     for (int32_t i = 0; i < n_jobs; ++i) {
-        if (jobs[i]->cfg.kind == KIND_RESIDENT || jobs[i]->cfg.kind == KIND_FUSED) resident.push_back(i);
+        if (jobs[i]->cfg.kind == KIND_RESIDENT || jobs[i]->cfg.kind == KIND_FUSED ||
+            jobs[i]->p.rob_eps > 0.f)
+            resident.push_back(i);
         else tiled.push_back(i);
     }
     if (tiled.empty() && resident.empty()) return RL_OK;

@@ -136,6 +136,7 @@ struct PhaseArgs {
     int64_t k;                     // base iteration index (plus LaunchArgs::kb)
     const float* tvg;              // phase B: TV denominator 1 - lambda div(...) or NULL
     int32_t wit;                   // sliding kernel: a span at least one strip long, or -1
+    float* store;                  // robust variant: store the window sum here and nothing else
 };
 
 // One launch covers the tiles of n_jobs jobs: job j owns workgroups
@@ -164,6 +165,7 @@ __device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
     p.sched = t->sched; p.active_total = t->active_total; p.act_part = t->act_part; p.k = t->k;
     p.tvg = t->tvg;
     p.wit = t->wit;
+    p.store = t->store;
     return p;
 }
 
@@ -353,6 +355,10 @@ __device__ __forceinline__ EpiIn epi_load(const PhaseArgs& p, size_t q) {
 template <bool PHASE_B>
 __device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, float val) {
     if (p.cnt && !(p.full || (int)e.c8 < p.hyst)) return 0;
+    if (p.store) {  // robust variant: the plain convolution or correlation
+        p.store[q] = val;
+        return 1;
+    }
     if (!PHASE_B) {
         p.r[q] = rl_ratio(e.x, val);
     } else {
@@ -1824,6 +1830,47 @@ __global__ __launch_bounds__(256) void tv_factor_kernel(const float* u, float* g
             d -= by;
         }
         g[q] = 1.f - lambda * d;
+    }
+}
+
+// Robust variant, between the forward convolution and the two correlations: from v (in
+// the r plane) and f, the weight w = 1 / sqrt(d + eps^2) of the I-divergence
+// d = v - f - f ln(v / f) (d = v where f = 0, d = 0 where v <= 0) and the weighted ratio
+// w f / v (0 where v <= 0), written over v.  d = f (x - ln(1 + x)) with x = (v - f) / f:
+// a short Taylor series below |x| = 0.1 (the direct difference cancels there), log1p
+// above.  The divisions and the square root are correctly rounded.
+__global__ __launch_bounds__(256) void robust_weights_kernel(float* r, const float* f, float* w,
+                                                             int64_t N, float eps2) {
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < N;
+         q += (int64_t)gridDim.x * 256) {
+        const float v = r[q], fq = f[q];
+        float d = 0.f, rq = 0.f;
+        if (v > 0.f) {
+            if (fq == 0.f) {
+                d = v;
+            } else {
+                const float x = __fdiv_rn(v - fq, fq);
+                float t;
+                if (fabsf(x) < 0.1f) {
+                    // x - ln(1 + x) = x^2 (1/2 - x/3 + x^2/4 - x^3/5 + x^4/6 - x^5/7 + x^6/8)
+                    float s = 0.125f;
+                    s = fmaf(s, x, -1.f / 7.f);
+                    s = fmaf(s, x, 1.f / 6.f);
+                    s = fmaf(s, x, -0.2f);
+                    s = fmaf(s, x, 0.25f);
+                    s = fmaf(s, x, -1.f / 3.f);
+                    s = fmaf(s, x, 0.5f);
+                    t = x * x * s;
+                } else {
+                    t = x - log1pf(x);
+                }
+                d = fq * t;
+            }
+            rq = __fdiv_rn(fq, v);
+        }
+        const float wq = __fdiv_rn(1.f, __fsqrt_rn(d + eps2));
+        w[q] = wq;
+        r[q] = wq * rq;
     }
 }
 

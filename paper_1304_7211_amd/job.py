@@ -15,7 +15,7 @@ def _stream_ptr(stream):
 
 
 def make_params(f, psf, boundary="reflect", path="auto", schedule="auto", kahan=True,
-                thin=None, u0=None, stream=None, tuning=None, tv=None):
+                thin=None, u0=None, stream=None, tuning=None, tv=None, robust=None):
     """Build an rl_params for a float32 CUDA image f (H, W) and a float32 numpy PSF."""
     if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float32
             and f.dim() == 2 and f.is_contiguous()):
@@ -47,6 +47,8 @@ def make_params(f, psf, boundary="reflect", path="auto", schedule="auto", kahan=
     if tv:
         p.tv_lambda = float(tv["lam"])
         p.tv_eps = float(tv.get("eps", 1e-3))
+    if robust:
+        p.rob_eps = float(robust["eps"])
     return p, psf  # keep psf alive until rl_init has copied it
 
 
@@ -78,9 +80,10 @@ def tune_lookup(f, psf, **kw):
 
 class Job:
     def __init__(self, f, psf, boundary="reflect", path="auto", schedule="auto", kahan=True,
-                 thin=None, u0=None, stream=None, workspace=None, tuning=None, tv=None):
+                 thin=None, u0=None, stream=None, workspace=None, tuning=None, tv=None,
+                 robust=None):
         p, keep = make_params(f, psf, boundary, path, schedule, kahan, thin, u0, stream, tuning,
-                              tv)
+                              tv, robust)
         self.nbytes = A.rl_workspace_bytes(p)
         if workspace is None:
             workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=f.device)

@@ -152,6 +152,24 @@ def test_workspace_bytes_and_validation(A):
     p, k13 = _params(A, thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
     p.tv_lambda, p.tv_eps = 0.1, 1e-3
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    # robust data term: eps >= 0; not with TV, thinning, the resident or fused schedule
+    p, k17 = _params(A)
+    p.rob_eps = 0.05
+    assert _ws_status(A, p)[0] == A.RL_OK
+    p.rob_eps = -1.0
+    assert _ws_status(A, p)[0] == A.RL_E_INVAL
+    p, k18 = _params(A, thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
+    p.rob_eps = 0.05
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k19 = _params(A)
+    p.rob_eps, p.tv_lambda, p.tv_eps = 0.05, 0.1, 1e-3
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k20 = _params(A, psf=synth.box_h(9), schedule=A.RL_SCHED_RESIDENT)
+    p.rob_eps = 0.05
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k21 = _params(A, psf=synth.box_h(9))  # auto schedule: two-pass for robust jobs
+    p.rob_eps = 0.05
+    assert _ws_status(A, p)[0] == A.RL_OK
     # summed-area rectangles: rectangle PSFs only, tables must fit in LDS
     p, k14 = _params(A, psf=synth.box_rect(5, 7), path=A.RL_PATH_BOX_SAT)
     assert _ws_status(A, p)[0] == A.RL_OK
