@@ -435,6 +435,13 @@ __device__ __forceinline__ TileGeom<ORIENT> make_geom(const PhaseArgs& p, int a0
 // (lanes are consecutive columns, so every access is coalesced), for ORIENT_ROWS the
 // elements the lane handles after the LDS transpose.  Loaded at kernel entry so that they
 // travel together with the tile.
+// Plain jobs on images whose width is a multiple of 4: the ROWS epilogue moves four
+// consecutive outputs per lane with 16-byte loads and stores.  (Thinned, TV and robust jobs
+// keep the per-output epilogue: a general four-wide one measured slower for every job.)
+__device__ __forceinline__ bool epi_vec(const PhaseArgs& p) {
+    return (p.W & 3) == 0 && !p.cnt && !p.tvg && !p.store;
+}
+
 template <int ORIENT, int S, int NW>
 struct EpiPlan {
     static constexpr int TB = NW * S;
@@ -460,6 +467,23 @@ __device__ __forceinline__ void epi_pos(int i, int a0, int b0, int& y, int& x) {
 template <int ORIENT, int S, int NW, bool PHASE_B>
 __device__ __forceinline__ void epi_prefetch(const PhaseArgs& p, int a0, int b0,
                                              EpiPlan<ORIENT, S, NW>& plan) {
+    if (ORIENT == ORIENT_ROWS && S % 4 == 0 && epi_vec(p)) {
+        constexpr int TB = NW * S;
+#pragma unroll
+        for (int j = 0; j < S / 4; ++j) {
+            const int flat = 4 * ((int)threadIdx.x + j * NW * 64);
+            const int y = a0 + flat / TB, x = b0 + flat % TB;
+            if (y < p.H && x < p.W) {
+                const float4 v = *reinterpret_cast<const float4*>(
+                    (PHASE_B ? p.u : p.f) + (size_t)y * p.W + x);
+                plan.in[4 * j].x = v.x;
+                plan.in[4 * j + 1].x = v.y;
+                plan.in[4 * j + 2].x = v.z;
+                plan.in[4 * j + 3].x = v.w;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < EpiPlan<ORIENT, S, NW>::PER; ++i) {
         int y, x;
@@ -491,6 +515,29 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
 #pragma unroll
         for (int s = 0; s < S; ++s) lds[lane * SP + wv * S + s] = out[s];
         __syncthreads();
+        if (S % 4 == 0 && epi_vec(p)) {
+#pragma unroll
+            for (int j = 0; j < S / 4; ++j) {
+                const int flat = 4 * ((int)threadIdx.x + j * NW * 64);
+                const int row = flat / TB, col = flat % TB;
+                const int y = a0 + row, x = b0 + col;
+                if (y < p.H && x < p.W) {
+                    const float* st = lds + row * SP + col;
+                    const EpiIn* e = &plan.in[4 * j];
+                    float4 o;
+                    if (!PHASE_B) {
+                        o = make_float4(rl_ratio(e[0].x, st[0]), rl_ratio(e[1].x, st[1]),
+                                        rl_ratio(e[2].x, st[2]), rl_ratio(e[3].x, st[3]));
+                        *reinterpret_cast<float4*>(p.r + (size_t)y * p.W + x) = o;
+                    } else {
+                        o = make_float4(__fmul_rn(e[0].x, st[0]), __fmul_rn(e[1].x, st[1]),
+                                        __fmul_rn(e[2].x, st[2]), __fmul_rn(e[3].x, st[3]));
+                        *reinterpret_cast<float4*>(p.u + (size_t)y * p.W + x) = o;
+                    }
+                }
+            }
+            return;  // plain jobs: no active count
+        }
 #pragma unroll
         for (int i = 0; i < EpiPlan<ORIENT, S, NW>::PER; ++i) {
             int e = threadIdx.x + i * NW * 64;
