@@ -78,13 +78,12 @@ __device__ __forceinline__ int fold_idx(int i, int n, int bc) {
 }
 
 // 1 for a non-zero value, 0 for +0 and -0 (inputs are >= 0 apart from the sign of zero,
-// so min(bits << 1, 1) does it in integer ops).  Sliding sums keep an exact integer count
-// of the non-zero inputs in their window next to the float running sum: every input is
-// >= 0, so a window sum is exactly 0 iff the count is 0, which the float sum -- after
+// so min(bits << 1, 1) does it in integer ops).  Every input is >= 0, so a window sum is
+// exactly 0 iff its count of non-zero inputs is 0, which a sliding float sum -- after
 // subtracting the larger values that left the window -- does not reproduce exactly.  Exact
 // zeros matter: v = 0 gives r = 0 where a near-zero v gives a huge ratio, and c = 0 gives
-// u^{k+1} = 0 exactly.  The counts are only kept in tiles whose inputs hold an exact zero
-// (tile_zeros below); elsewhere every window sum is positive anyway.
+// u^{k+1} = 0 exactly.  The sliding kernels therefore count non-zero inputs where an
+// all-zero window is possible (witness inputs or tile_zeros below decide where).
 __device__ __forceinline__ int nz(float x) { return (int)min(__float_as_uint(x) << 1, 1u); }
 
 // Kahan-compensated accumulation: s + x with running compensation c.
