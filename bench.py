@@ -24,10 +24,10 @@ configuration:
   4  256 uneven images (sides log-uniform 256..2048, mixed PSFs, 100..300 iterations) in
      one batch: throughput with compensated and plain float32 sums, and the error of both
      against the FP64 oracle on the two cheapest jobs of each PSF class;
-  5  serving: Poisson arrivals of requests drawn from a pool (sides 128..4096, mixed
+  5  serving: Poisson arrivals of 1000 requests drawn from a pool (sides 128..4096, mixed
      PSFs, 50..500 iterations, thinning on) at 70 % of the measured batched capacity:
      p50/p99 latency and throughput of the continuous-batching server against the plain
-     one-at-a-time method on the same GPU;
+     one-at-a-time method on the same GPU, then the server alone at 50 % and 90 % load;
   6  rectangle PSFs (5x7, 15x15, 31x31, 63x9) at 1024^2 and 2048^2, 100 iterations: the
      separable BOX_RECT kernels and the summed-area BOX_SAT kernels against the per-row
      sliding runs, px-it/s, per-launch kernel time and HBM fraction of the phase kernels.
@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="also time the other mode (reported as 'other_mode')")
     ap.add_argument("--report", type=int, choices=[1, 3, 4, 5, 6], default=None)
-    ap.add_argument("--requests", type=int, default=48, help="--report 5: requests")
+    ap.add_argument("--requests", type=int, default=1000, help="--report 5: requests")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the "
                          "reference dispatch for scaling HBM counters)")
@@ -549,6 +549,18 @@ def report_serving(args, dev):
     same = all(torch.equal(a.result, b.result) for a, b in zip(reqs, base))
     px_it = sum(pool[i % len(pool)][0].size * pool[i % len(pool)][2] for i in range(n))
     log(f"report 5: continuous {rep_c}, plain {rep_p}, identical={same}")
+    del base
+    # load sweep of the continuous-batching server (same request mix, other arrival rates)
+    sweep = []
+    for frac in (0.5, 0.9):
+        arr = np.cumsum(rng.exponential(1.0 / (frac * capacity), size=n))
+        rs = make(n, arr)
+        sv = Server(budget, max_slots=64, chunk=10)
+        dt_s = run_stream(rs, sv)
+        sweep.append(dict(load=frac, qps=frac * capacity, latency=latency_report(rs),
+                          px_it_per_s=px_it / dt_s))
+        log(f"report 5: load {frac}: {sweep[-1]['latency']}")
+        del rs
     return {
         "report": "serving, config 5",
         "workload": f"{n} requests from a pool of {len(pool)} (sides 128..4096, mixed PSFs, "
@@ -559,6 +571,7 @@ def report_serving(args, dev):
                            peak_slots=srv.ctl.peak_slots),
         "plain_per_image": dict(latency=rep_p, wall_s=dt_p, px_it_per_s=px_it / dt_p),
         "results_identical": bool(same),
+        "load_sweep": sweep,
     }
 
 
