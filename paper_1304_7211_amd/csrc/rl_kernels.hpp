@@ -880,6 +880,31 @@ __host__ __device__ constexpr size_t rect_lds_floats(int ny, int nx, int TB) {
     return (size_t)ny * (nx | 1) + (size_t)ny * rect_hs_pitch<NW>(TB) + NW;
 }
 
+// Whether a rectangle tile needs the exact non-zero counts (see rect_tile).  For kh < 8
+// the flags were published by note_zeros before the first barrier; otherwise every
+// vertical task checks its witness inputs here, with one more barrier.
+template <int NW>
+__device__ __forceinline__ bool rect_need_counts(const float* lds, int pitch, int kh, int kw,
+                                                 int vr, int vb, bool has_v, int* zf) {
+    if (kh >= RECT_SEG) {
+        bool bad = false;
+        if (has_v) {
+            float m = 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int r = vr * RECT_SEG + RECT_SEG - 1 + ((kh - RECT_SEG) * t) / 3;
+                const int c = vb + ((kw - 1) * t) / 3;
+                m = fmaxf(m, fabsf(lds[r * pitch + c]));
+            }
+            bad = !(m > 0.f);
+        }
+        const bool any = __ballot(bad) != 0ull;
+        if ((threadIdx.x & 63) == 0) zf[wave_id()] = any ? 1 : 0;
+        __syncthreads();
+    }
+    return tile_zeros<NW>(zf);
+}
+
 template <int S, int NW, bool PHASE_B>
 __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, float* lds) {
     constexpr int TB = NW * S;
@@ -906,9 +931,8 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
     load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
     lds_dma_wait();
     int* zf = reinterpret_cast<int*>(lds + rect_lds_floats<NW>(ny, nx, TB) - NW);
-    note_zeros(lds, ny, nx, pitch, zf);
+    if (kh < RECT_SEG) note_zeros(lds, ny, nx, pitch, zf);
     __syncthreads();
-    const bool cnt = tile_zeros<NW>(zf);  // the same for the whole workgroup
     // horizontal pass
     for (int task = tid; task < ny * NSEG_H; task += NW * 64) {
         const int r = task / NSEG_H, c0 = (task % NSEG_H) * RECT_SEG;
@@ -953,8 +977,13 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
             v[j] = sum - comp;
         }
     }
-    // Exact zeros (tiles holding a zero): the same two passes over non-zero counts, the
-    // horizontal ones in place of the sums, and windows with none give exactly 0.
+    // Exact zeros: the same two passes over non-zero counts (the horizontal ones in place
+    // of the sums), windows with none give exactly 0.  They run only where an all-zero
+    // window is possible: with kh >= 8, tile rows 8 vr + 7 .. 8 vr + kh - 1 lie in all
+    // 8 windows of a vertical task, and a non-zero input among four of them (on the
+    // task's columns) proves that none of its windows is all-zero; with kh < 8, in tiles
+    // that hold a zero.  The decision is the same for the whole workgroup.
+    const bool cnt = rect_need_counts<NW>(lds, pitch, kh, kw, vr, vb, has_v, zf);
     if (cnt) {
         int* hn = reinterpret_cast<int*>(hs);
         __syncthreads();  // everyone is done reading the sums
@@ -1057,9 +1086,8 @@ __device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, flo
     load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
     lds_dma_wait();
     int* zf = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + sat_lds_bytes<NW>(ny, nx)) - NW;
-    note_zeros(lds, ny, nx, pitch, zf);
+    if (kh < RECT_SEG) note_zeros(lds, ny, nx, pitch, zf);
     __syncthreads();
-    const bool cnt = tile_zeros<NW>(zf);  // the same for the whole workgroup
     // row 0 of T is 0; each row's prefix starts at column 0 = 0
     for (int j = tid; j <= nx; j += NW * 64) T[j] = 0.0;
     // row prefix sums: T(i + 1, j + 1) = sum of tile row i, columns 0..j
@@ -1107,6 +1135,8 @@ __device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, flo
             T[(size_t)i * tp + j] = s;
         }
     }
+    // exact zeros: decided as in the rectangle kernel (witness inputs or the tile scan)
+    const bool cnt = rect_need_counts<NW>(lds, pitch, kh, kw, vr, vb, has_v, zf);
     if (cnt) {
         // row prefixes of the non-zero counts, each overwriting its own tile row (the
         // values are not needed any more): N(i, j) counts row i, columns 0..j
