@@ -69,6 +69,8 @@ ZERO_CASES = [("disc3", lambda: synth.disc(3), [("direct", "auto"), ("runs", "au
                                                   ("box_axis", "resident")]),
               ("rect5x4", lambda: synth.box_rect(5, 4), [("box_rect", "auto"), ("box_sat", "auto"),
                                                          ("runs", "auto")]),
+              ("rect12x7", lambda: synth.box_rect(12, 7), [("box_rect", "auto"),
+                                                           ("box_sat", "auto")]),
               ("oblique13", lambda: synth.oblique_line(13, 35.0), [("runs", "auto")])]
 
 
@@ -118,7 +120,9 @@ SPARSE_CASES = [("disc5", lambda: synth.disc(5), [("runs", "auto"), ("direct", "
                 ("box_v11", lambda: synth.box_v(11), [("box_axis", "two_pass"),
                                                       ("box_axis", "resident")]),
                 ("rect6x9", lambda: synth.box_rect(6, 9), [("box_rect", "auto"),
-                                                           ("box_sat", "auto"), ("runs", "auto")])]
+                                                           ("box_sat", "auto"), ("runs", "auto")]),
+                ("rect11x5", lambda: synth.box_rect(11, 5), [("box_rect", "auto"),
+                                                             ("box_sat", "auto")])]
 
 
 @pytest.mark.parametrize("density", [0.5, 0.9])
