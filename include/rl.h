@@ -79,10 +79,11 @@ typedef int32_t rl_status;
 #define RL_SCHED_FUSED 3    /* one kernel per iteration: conv, ratio, corr and update on an
                                LDS tile with a double halo (u double-buffered); plain jobs
                                with height, width >= 64 and PSF extents <= 63 only         */
-#define RL_SCHED_PERSISTENT 4 /* reserved: one launch per rl_iterate call running both
-                               phases of every iteration, tiles synchronised through
-                               per-tile step counters.  Currently switched off: every
-                               call asking for it returns RL_E_UNSUPPORTED.              */
+#define RL_SCHED_PERSISTENT 4 /* one launch per rl_iterate call running both phases of
+                               every iteration, tiles synchronised through per-tile step
+                               counters; plain RL on the span and sliding kernels (strips
+                               of 4 or 8) only, else RL_E_UNSUPPORTED.  Inside
+                               rl_iterate_batch such jobs run on the two-pass kernels.   */
 
 /* thinning (Section 4) */
 #define RL_THIN_OFF 0

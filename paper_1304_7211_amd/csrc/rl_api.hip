@@ -201,9 +201,8 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
         *why = "the robust data term runs on the two-pass schedule, without TV or thinning";
         return RL_E_UNSUPPORTED;
     }
-    if (sched == RL_SCHED_PERSISTENT) {
-        // Switched off: its first GPU run did not finish, and no cause has been shown yet.
-        *why = "the persistent schedule is switched off";
+    if (sched == RL_SCHED_PERSISTENT && (thin || tv || rob)) {
+        *why = "the persistent schedule serves plain RL";
         return RL_E_UNSUPPORTED;
     }
     if (sched == RL_SCHED_FUSED) {
@@ -397,6 +396,10 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     cfg->tiles_a = (la + cfg->TA - 1) / cfg->TA;
     cfg->tiles_b = (lb + cfg->TB - 1) / cfg->TB;
     if (cfg->sched == RL_SCHED_PERSISTENT) {
+        if (cfg->kind != KIND_SPAN && cfg->kind != KIND_SLIDE) {
+            *why = "the persistent schedule runs the span and sliding kernels";
+            return RL_E_UNSUPPORTED;
+        }
         if (cfg->S != 4 && cfg->S != 8) { *why = "the persistent schedule runs strips of 4 or 8"; return RL_E_UNSUPPORTED; }
         // tiles whose data a tile's halo can reach, on each axis; a fold deeper than the
         // image can reach anywhere on that axis
@@ -650,7 +653,7 @@ int persist_capacity(PersistFn fn, size_t lds) {
     return std::max(1, per_cu) * std::max(1, cus);
 }
 
-constexpr int kSpinLimit = 1 << 22;  // polls before a persistent launch gives up
+constexpr int kSpinLimit = 1 << 20;  // polls (about a second) before a persistent launch gives up
 
 PhaseFn phase_fn(const Config& c, bool phase_b) {
     if (c.kind == KIND_RECT) {

@@ -1205,10 +1205,20 @@ __global__ __launch_bounds__(NW * 64) void sat_kernel(LaunchArgs L) {
 // halo's reach has finished step s - 1 (done[t'] >= s): that covers the data it reads
 // (u^k from phase B, or r from phase A) and the data it overwrites (which those tiles read
 // in step s - 1).  Completion: every wavefront waits for its stores, the workgroup
-// synchronises, and one lane publishes done[t] = s + 1 after an agent-scope release (the
-// XCDs have separate L2 caches); the waiting side polls with relaxed agent-scope loads and
-// then takes an agent-scope acquire before reading.  Waits are bounded: past spin_limit
-// polls the launch raises *abort and every workgroup leaves, so the kernel always ends.
+// synchronises, and wavefront 0 publishes done[t] = s + 1 after an agent-scope release
+// (the XCDs have separate L2 caches); the waiting side polls with relaxed agent-scope
+// loads and then takes an agent-scope acquire before reading.
+//
+// Wavefront 0 as a whole takes the ticket, waits and publishes, under a condition that is
+// uniform per wavefront (wave_id() goes through readfirstlane), and its lanes write
+// identical values; only the ticket's atomic add runs on a single lane, inside a short
+// branch that rejoins before anything else.  No lane-divergent region may span the loop's
+// back edge: if lane 0 alone published and took the next ticket, the compiler may lay the
+// loop out so that lanes 1..63 of wavefront 0 return to the barrier without lane 0, and
+// the workgroup then re-reads the previous task from LDS and repeats that tile without
+// end.  Waits are bounded: past spin_limit polls the launch raises *abort and every
+// workgroup leaves; each pass of the loop takes a new ticket or leaves, so the loop runs
+// at most total + 1 passes and the kernel always ends.
 // ---------------------------------------------------------------------------------------
 struct PersistJob {
     PhaseArgs a, b;        // phase A / phase B records (k = iteration index at launch)
@@ -1245,43 +1255,51 @@ __device__ __forceinline__ int poll_done(int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0: wait until every tile in the reach of tile t has finished step s - 1.
-// Returns false if the launch is being aborted.
+// Wavefront 0, all lanes: wait until every tile in the reach of tile t has finished step
+// s - 1.  Lane l checks the tiles l, l + 64, ... of the reach rectangle; the wavefront
+// decides together (ballot), so the result and the loop are wavefront-uniform.  Returns
+// false if the launch is being aborted.
 __device__ __forceinline__ bool wait_deps(const PersistJob& J, int t, int s, int spin_limit,
                                           int32_t* abort) {
     if (s == 0) return true;
+    const int lane = threadIdx.x & 63;
     const int ta_n = J.a.tiles_a, tb_n = J.a.tiles_b;
     const int ta = t % ta_n, tb = t / ta_n;
     const int a_lo = max(0, ta - J.reach_a), a_hi = min(ta_n - 1, ta + J.reach_a);
     const int b_lo = max(0, tb - J.reach_b), b_hi = min(tb_n - 1, tb + J.reach_b);
-    int spins = 0;
-    for (int y = b_lo; y <= b_hi; ++y) {
-        for (int x = a_lo; x <= a_hi; ++x) {
-            int32_t* d = J.done + y * ta_n + x;
-            while (poll_done(d) < s) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > spin_limit) {
-                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    return false;
-                }
-                if ((spins & 1023) == 0 && poll_done(abort)) return false;
-            }
+    const int na = a_hi - a_lo + 1, nd = na * (b_hi - b_lo + 1);
+    for (int spins = 0;; ++spins) {
+        bool ready = true;
+        for (int d = lane; d < nd; d += 64) {
+            const int y = b_lo + d / na, x = a_lo + d % na;
+            if (poll_done(J.done + y * ta_n + x) < s) ready = false;
         }
+        if (__ballot(!ready) == 0ull) return true;
+        if (spins >= spin_limit) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if ((spins & 1023) == 1023 &&
+            __builtin_amdgcn_readfirstlane(poll_done(abort)) != 0)
+            return false;
+        __builtin_amdgcn_s_sleep(2);
     }
-    return true;
 }
 
 template <int KIND, int ORIENT, int S, int LMAX, int NW>
 __global__ __launch_bounds__(NW * 64) void persist_kernel(PersistArgs P) {
     extern __shared__ float lds[];
-    __shared__ int32_t task[3];  // job, tile, step (job < 0: leave)
+    __shared__ int32_t task[3];  // job, tile, step (job -1: leave, -2: nothing to do)
     constexpr int TA = 64, TB = NW * S;
     const int64_t total = (int64_t)P.max_steps * P.total_tiles;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const int q = atomicAdd(P.ticket, 1);
+    const bool lead = wave_id() == 0;  // wavefront-uniform
+    for (int64_t pass = 0; pass <= total; ++pass) {
+        if (lead) {
+            int q = 0;
+            if ((threadIdx.x & 63) == 0) q = atomicAdd(P.ticket, 1);
+            q = __builtin_amdgcn_readfirstlane(q);
             int jn = -1, t = 0, st = 0;
-            if (q < total && !poll_done(P.abort)) {
+            if (q < total && __builtin_amdgcn_readfirstlane(poll_done(P.abort)) == 0) {
                 st = q / P.total_tiles;
                 const int idx = q - st * P.total_tiles;
                 int lo = 0;
@@ -1307,13 +1325,13 @@ __global__ __launch_bounds__(NW * 64) void persist_kernel(PersistArgs P) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
             }
-            task[0] = jn;
+            task[0] = jn;  // every lane of wavefront 0 writes the same values
             task[1] = t;
             task[2] = st;
         }
         __syncthreads();
         const int jn = task[0], t = task[1], st = task[2];
-        __syncthreads();  // task[] is rewritten at the next loop top
+        __syncthreads();  // task[] is rewritten at the next pass
         if (jn == -1) break;
         if (jn == -2) continue;
         const PersistJob J = P.n_jobs > 1 ? load_persist((ConstPersistPtr)P.jobs + jn) : P.one;
@@ -1331,7 +1349,7 @@ __global__ __launch_bounds__(NW * 64) void persist_kernel(PersistArgs P) {
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wavefront's stores have reached L2
         __syncthreads();                // every wavefront's have; LDS is free again
-        if (threadIdx.x == 0) {
+        if (lead) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // visible to every XCD
             __hip_atomic_store(J.done + t, st + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }

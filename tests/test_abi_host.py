@@ -177,8 +177,22 @@ def test_workspace_bytes_and_validation(A):
     assert _ws_status(A, p)[0] == A.RL_E_INVAL
     p, k16 = _params(A, psf=synth.box_rect(127, 101), path=A.RL_PATH_BOX_SAT)
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
-    # the persistent schedule is switched off
+    # the persistent schedule: plain RL on the span and sliding kernels only
     p, k10 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT)
+    assert _ws_status(A, p)[0] == A.RL_OK
+    p, k22 = _params(A, psf=synth.oblique_line(15, 30.0), schedule=A.RL_SCHED_PERSISTENT)
+    assert _ws_status(A, p)[0] == A.RL_OK
+    p, k23 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT,
+                     thin=(A.RL_THIN_REL, 1e-4, 5, 10, 10))
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k24 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT)
+    p.tv_lambda, p.tv_eps = 0.1, 1e-3
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k25 = _params(A, psf=synth.disc(5), schedule=A.RL_SCHED_PERSISTENT)
+    p.rob_eps = 0.05
+    assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
+    p, k26 = _params(A, psf=synth.box_rect(5, 7), path=A.RL_PATH_BOX_RECT,
+                     schedule=A.RL_SCHED_PERSISTENT)
     assert _ws_status(A, p)[0] == A.RL_E_UNSUPPORTED
     p, k11 = _params(A, schedule=9)
     assert _ws_status(A, p)[0] == A.RL_E_INVAL

@@ -12,9 +12,7 @@ import pytest
 import synth
 from gpu_util import RTOL, rel_err, run_gpu, to_dev
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="persistent schedule switched off: its first GPU run "
-                                      "did not finish and no cause has been shown")]
+pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
