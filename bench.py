@@ -485,6 +485,22 @@ def report_batched(args, dev):
                 np.max(np.abs(u - ref) / np.maximum(np.abs(ref), 1e-4)))
         errs.append(dict(job=j["name"], shape=list(j["f"].shape), iters=j["iters"], **e))
         log(f"report 4: {errs[-1]}")
+    # one lock-step iteration on every job: from the GPU's float32 state u^K, one more GPU
+    # iteration in one batch call against one FP64 oracle iteration from the same state
+    t2 = time.perf_counter()
+    js = [Job(f, j["psf"], u0=out[True]["u"][i]) for i, (j, f) in enumerate(zip(jobs, fs))]
+    runner.iterate(js, [1] * len(js))
+    lock = []
+    for i, (j, jb) in enumerate(zip(jobs, js)):
+        u1 = jb.result().cpu().numpy().astype(np.float64)
+        ref = o.rl(j["f"], j["psf"], 1, u0=out[True]["u"][i].cpu().numpy())
+        lock.append(float(np.max(np.abs(u1 - ref) / np.maximum(np.abs(ref), 1e-4))))
+        jb.close()
+        if (i + 1) % 32 == 0:
+            log(f"report 4: lock-step {i + 1}/{len(jobs)} jobs checked")
+    worst = int(np.argmax(lock))
+    log(f"report 4: lock-step iteration on {len(lock)} jobs in {time.perf_counter() - t2:.1f}s, "
+        f"max rel err {lock[worst]:.3g} ({jobs[worst]['name']})")
     return {
         "report": "batched uneven jobs, config 4",
         "workload": "256 images, sides log-uniform 256..2048, PSFs axis/oblique/disc/dense15, "
@@ -496,6 +512,8 @@ def report_batched(args, dev):
             "compensated": max(e["compensated"] for e in errs),
             "plain": max(e["plain"] for e in errs)},
         "checked_jobs": errs,
+        "lockstep_all_jobs": {"jobs": len(lock), "max_rel_err": max(lock),
+                              "worst_job": jobs[worst]["name"]},
     }
 
 
