@@ -14,9 +14,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librl.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# Packed FP32 instructions are switched off for all device code (v_pk_* FP32 forms are
-# not trusted on the test machines); the host pass warns that it does not know the
-# feature, which is harmless.
+# Packed FP32 instructions are switched off for all device code (some v_pk_* FP32 forms
+# have been seen to give wrong results without any error); the host pass warns that it
+# does not know the feature, which is harmless.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument",
