@@ -629,7 +629,7 @@ def summarize_trace(trace_dir, bench_log, command):
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     out += ["", "bench.py's own per-kernel durations (dispatch-attached events, same workload, "
-            "same box, run without the profiler just before):", ""]
+            "same machine, run without the profiler just before):", ""]
     for k, v in bench.get("kernels", {}).items():
         out.append(f"- `{k}`: {v['avg_us']:.2f} us over {v['launches']} launches")
     rf = bench.get("roofline") or {}
