@@ -30,7 +30,11 @@ configuration:
      one-at-a-time method on the same GPU, then the server alone at 50 % and 90 % load;
   6  rectangle PSFs (5x7, 15x15, 31x31, 63x9) at 1024^2 and 2048^2, 100 iterations: the
      separable BOX_RECT kernels and the summed-area BOX_SAT kernels against the per-row
-     sliding runs, px-it/s, per-launch kernel time and HBM fraction of the phase kernels.
+     sliding runs, px-it/s, per-launch kernel time and HBM fraction of the phase kernels;
+  7  image-size sweep of the headline PSFs (oblique line 31 at 30 degrees, disc r=10) at
+     512^2 .. 4096^2, 50 iterations, two-pass schedule: px-it/s, per-launch kernel time and
+     HBM fraction of each phase kernel, to show how the fixed latency of a launch weighs
+     at each size.
 """
 import argparse
 import json
@@ -120,7 +124,7 @@ def main():
     ap.add_argument("--mode", choices=["batch", "sequential"], default="batch")
     ap.add_argument("--compare", action="store_true",
                     help="also time the other mode (reported as 'other_mode')")
-    ap.add_argument("--report", type=int, choices=[1, 3, 4, 5, 6], default=None)
+    ap.add_argument("--report", type=int, choices=[1, 3, 4, 5, 6, 7], default=None)
     ap.add_argument("--requests", type=int, default=1000, help="--report 5: requests")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the "
@@ -169,7 +173,7 @@ def main():
         del src, dst
     if args.report:
         line = {1: report_plain_small, 3: report_thinned, 4: report_batched,
-                5: report_serving, 6: report_rect}[args.report](args, dev)
+                5: report_serving, 6: report_rect, 7: report_sizes}[args.report](args, dev)
         print(json.dumps(line), flush=True)
         return
     jobs = synth.job_for_config(2)
@@ -742,6 +746,52 @@ def report_rect(args, dev):
             log(f"report 6: {row}")
     return {"report": "rectangle PSFs: separable BOX_RECT and summed-area BOX_SAT vs sliding runs",
             "iterations": K, "rows": rows}
+
+
+def report_sizes(args, dev):
+    import torch
+
+    import synth
+    from paper_1304_7211_amd import _abi as A
+    from paper_1304_7211_amd.job import Job
+    K = 50
+    rows = []
+    for name, h in (("oblique-31-at-30deg", synth.oblique_line(31, 30.0)),
+                    ("disc-r10", synth.disc(10))):
+        for side in (512, 1024, 2048, 4096):
+            f = torch.from_numpy(synth.observe(synth.latent_image(side, side, 7), h,
+                                               "gaussian", 7)).to(dev)
+            j = Job(f, h, path="runs")
+            j.iterate(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            j.iterate(K)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            A.rl_timing_reset()
+            A.rl_timing_enable(True)
+            j.iterate(10)
+            torch.cuda.synchronize()
+            A.rl_timing_enable(False)
+            kernels = {}
+            for nm in ("slide_conv_ratio", "slide_corr_update", "span_conv_ratio",
+                       "span_corr_update"):
+                n, ms = A.rl_timing_read(nm)
+                if n:
+                    us = 1e3 * ms / n
+                    kernels[nm] = dict(us=round(us, 2), hbm_frac=round(
+                        BYTES_PER_PX_PHASE * side * side / (us * 1e-6) / (PEAK_HBM_GBS * 1e9), 4))
+            A.rl_timing_reset()
+            strip = j.describe()["strip"]
+            j.close()
+            del f
+            row = dict(psf=name, side=side, strip=strip, px_it_per_s=side * side * K / dt,
+                       us_per_it=round(1e6 * dt / K, 2), kernels=kernels)
+            rows.append(row)
+            log(f"report 7: {row}")
+    return {"report": "image-size sweep of the phase kernels (two-pass schedule)",
+            "iterations": K, "bytes_per_px_per_phase": BYTES_PER_PX_PHASE,
+            "peak_hbm_gbs": PEAK_HBM_GBS, "rows": rows}
 
 
 def cpu_baseline(jobs):
