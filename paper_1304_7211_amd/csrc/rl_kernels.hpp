@@ -563,11 +563,8 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
 // table is the DIRECT path.
 // ---------------------------------------------------------------------------------------
 template <int ORIENT, int S, int L>
-__device__ __forceinline__ void span_piece(const float* base, const TileGeom<ORIENT>& g,
-                                           ConstFloatPtr wp, float (&part)[S]) {
-    float w[L];
-#pragma unroll
-    for (int t = 0; t < L; ++t) w[t] = wp[t];
+__device__ __forceinline__ void span_piece_w(const float* base, const TileGeom<ORIENT>& g,
+                                             const float* w, float (&part)[S]) {
     float win[S + L - 1];
     const int st = g.bstep();
 #pragma unroll
@@ -579,6 +576,15 @@ __device__ __forceinline__ void span_piece(const float* base, const TileGeom<ORI
         for (int t = 0; t < L; ++t) a = fmaf(w[t], win[s + t], a);
         part[s] = a;
     }
+}
+
+template <int ORIENT, int S, int L>
+__device__ __forceinline__ void span_piece(const float* base, const TileGeom<ORIENT>& g,
+                                           ConstFloatPtr wp, float (&part)[S]) {
+    float w[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) w[t] = wp[t];
+    span_piece_w<ORIENT, S, L>(base, g, w, part);
 }
 
 // One output tile of a phase (span kernel): tile origin (a0, b0) on the lane and strip
@@ -605,14 +611,22 @@ __device__ __forceinline__ void span_tile(const PhaseArgs& p, int a0, int b0, fl
 
     const ConstSpanPtr spans = as_const(p.spans);
     const ConstFloatPtr wts = as_const(p.wts);
+    // one span of lookahead: the current span's LMAX weights (the weight table carries 16
+    // zeros past its end) and the next span's descriptor (the span table carries one zero
+    // descriptor past its end) are loaded together, so each span waits for one scalar
+    // round trip instead of two in a row
+    DevSpan nsp = load_span(spans, 0);
     for (int i = 0; i < p.n_spans; ++i) {
-        const DevSpan sp = load_span(spans, i);
-        const ConstFloatPtr wp = wts + sp.woff;
+        const DevSpan sp = nsp;
+        float wl[LMAX];
+#pragma unroll
+        for (int t = 0; t < LMAX; ++t) wl[t] = wts[sp.woff + t];
+        nsp = load_span(spans, i + 1);
         const float* base = lane_lds + g.uni_part(sp.lane_off, lb + sp.c0);
         switch (sp.len) {
 #define RL_PIECE(n) \
     case n:         \
-        if (n <= LMAX) span_piece<ORIENT, S, (n <= LMAX ? n : 1)>(base, g, wp, part); \
+        if (n <= LMAX) span_piece_w<ORIENT, S, (n <= LMAX ? n : 1)>(base, g, wl, part); \
         break;
             RL_PIECE(1) RL_PIECE(2) RL_PIECE(3) RL_PIECE(4) RL_PIECE(5) RL_PIECE(6)
             RL_PIECE(7) RL_PIECE(8) RL_PIECE(9) RL_PIECE(10) RL_PIECE(11) RL_PIECE(12)
