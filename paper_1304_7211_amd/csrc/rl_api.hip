@@ -33,6 +33,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
+constexpr size_t kSpanPad = 2;  // zero descriptors after each span table (read-ahead)
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
@@ -422,10 +423,11 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     L.u = take(N * 4);
     L.r = take(N * 4);
     const size_t pad = 16;  // zero weights after the table (span kernel over-reads <= 15)
-    // one zero descriptor after each span table: the span kernel reads one entry ahead
-    L.conv_spans = take((cfg.conv.spans.size() + 1) * sizeof(DevSpan));
+    // zero descriptors after each span table: the span and sliding kernels read up to
+    // kSpanPad entries ahead
+    L.conv_spans = take((cfg.conv.spans.size() + kSpanPad) * sizeof(DevSpan));
     L.conv_w = take((cfg.conv.w.size() + pad) * 4);
-    L.corr_spans = take((cfg.corr.spans.size() + 1) * sizeof(DevSpan));
+    L.corr_spans = take((cfg.corr.spans.size() + kSpanPad) * sizeof(DevSpan));
     L.corr_w = take((cfg.corr.w.size() + pad) * 4);
     const size_t ntiles = (size_t)cfg.tiles_a * cfg.tiles_b;
     if (thin) {
@@ -1185,8 +1187,8 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     // compiled PSF tables -> workspace (host copies stay alive in the job)
     j->h_conv = to_dev(j->cfg.conv);
     j->h_corr = to_dev(j->cfg.corr);
-    j->h_conv.push_back(DevSpan{});
-    j->h_corr.push_back(DevSpan{});
+    j->h_conv.resize(j->h_conv.size() + kSpanPad, DevSpan{});
+    j->h_corr.resize(j->h_corr.size() + kSpanPad, DevSpan{});
     j->h_conv_w = j->cfg.conv.w;
     j->h_conv_w.resize(j->h_conv_w.size() + 16, 0.f);
     j->h_corr_w = j->cfg.corr.w;

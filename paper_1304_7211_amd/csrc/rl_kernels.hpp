@@ -708,19 +708,27 @@ __device__ __forceinline__ void slide_steps(const PhaseArgs& p, const float* lds
         else seed = fmaf(sp.w0, part, seed);
     }
     // per-step changes d[s] (step into output s of the strip), accumulated over the spans
-    // in increasing order; U spans per loop trip so that their descriptor and LDS reads are
-    // in flight together.  The first wavefront's d[0] is not a step (its first output is
-    // the seed): it reads an in-tile neighbour instead and is cleared afterwards.
+    // in increasing order; U spans per loop trip so that their LDS reads are in flight
+    // together, and the next trip's descriptors are loaded one trip ahead (the span table
+    // carries zero descriptors past its end).  The first wavefront's d[0] is not a step
+    // (its first output is the seed): it reads an in-tile neighbour instead and is cleared
+    // afterwards.
     constexpr int U = S <= 8 ? 2 : 1;
     float d[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) d[s] = 0.f;
     const int z0 = wv == 0 ? 1 : 0;
     int i = 0;
+    DevSpan nsp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) nsp[u] = load_span(spans, u);
     for (; i + U <= p.n_spans; i += U) {
         DevSpan sp[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) sp[u] = load_span(spans, i + u);
+        for (int u = 0; u < U; ++u) {
+            sp[u] = nsp[u];
+            nsp[u] = load_span(spans, i + U + u);
+        }
         float din[U][S], dout[U][S];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
