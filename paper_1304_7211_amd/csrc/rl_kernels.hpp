@@ -612,8 +612,8 @@ __device__ __forceinline__ void span_tile(const PhaseArgs& p, int a0, int b0, fl
     const ConstSpanPtr spans = as_const(p.spans);
     const ConstFloatPtr wts = as_const(p.wts);
     // one span of lookahead: the current span's LMAX weights (the weight table carries 16
-    // zeros past its end) and the next span's descriptor (the span table carries one zero
-    // descriptor past its end) are loaded together, so each span waits for one scalar
+    // zeros past its end) and the next span's descriptor (the span table carries zero
+    // descriptors past its end) are loaded together, so each span waits for one scalar
     // round trip instead of two in a row
     DevSpan nsp = load_span(spans, 0);
     for (int i = 0; i < p.n_spans; ++i) {
