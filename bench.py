@@ -126,6 +126,11 @@ def main():
                     help="also time the other mode (reported as 'other_mode')")
     ap.add_argument("--report", type=int, choices=[1, 3, 4, 5, 6, 7], default=None)
     ap.add_argument("--requests", type=int, default=1000, help="--report 5: requests")
+    ap.add_argument("--sides", default="512,1024,2048,4096",
+                    help="--report 7: image sides, comma-separated")
+    ap.add_argument("--summary-side", type=int, default=0,
+                    help="--summarize-pmc / --summarize-trace: the profiled run was "
+                         "--report 7 --sides N with this N (default: the benchmark workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the "
                          "reference dispatch for scaling HBM counters)")
@@ -143,11 +148,11 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
-                            args.calibrate_copy, args.pmc_command))
+                            args.calibrate_copy, args.pmc_command, args.summary_side))
         return
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace[0], args.summarize_trace[1],
-                              args.pmc_command))
+                              args.pmc_command, args.summary_side))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -612,20 +617,28 @@ def _timing_name(kernel):
     return f"{kind}_{'corr_update' if phase_b else 'conv_ratio'}"
 
 
-def summarize_trace(trace_dir, bench_log, command):
+def summarize_trace(trace_dir, bench_log, command, side=0):
     """Per-kernel durations from rocprofv3's kernel statistics, next to bench.py's own
-    dispatch-event durations of an unprofiled run of the same workload."""
+    dispatch-event durations of an unprofiled run of the same workload (the benchmark, or
+    with side > 0 the size sweep of --report 7 at that side)."""
     import csv
     import glob
     fn = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
     rows = list(csv.DictReader(open(fn)))
     line = [ln for ln in open(bench_log).read().splitlines() if ln.startswith("{")][-1]
     bench = json.loads(line)
-    out = ["# Kernel trace: bench.py default workload (specialised PSFs, 3 x 1024x1024, "
-           "200 iterations, batch mode)", "", "Command:", "", "```", command.strip(), "```", "",
-           "The run covers bench.py's warmup step, its timed steps and its instrumented "
-           "steps. rocprofv3 lengthens the uninstrumented timing, so the headline value "
-           "comes from runs without the profiler.", "",
+    if side:
+        title = (f"# Kernel trace: phase kernels at {side}x{side} (oblique line 31 at 30 deg "
+                 f"and disc r=10, two-pass, bench.py --report 7 --sides {side})")
+        note = ("The run covers the report's warmup, timed and instrumented iterations of "
+                "both PSFs.")
+    else:
+        title = ("# Kernel trace: bench.py default workload (specialised PSFs, 3 x 1024x1024, "
+                 "200 iterations, batch mode)")
+        note = ("The run covers bench.py's warmup step, its timed steps and its instrumented "
+                "steps. rocprofv3 lengthens the uninstrumented timing, so the headline value "
+                "comes from runs without the profiler.")
+    out = [title, "", "Command:", "", "```", command.strip(), "```", "", note, "",
            "| Kernel | calls | total ms | avg us | min us | max us | % |",
            "|---|---|---|---|---|---|---|"]
     for r in rows:
@@ -634,6 +647,12 @@ def summarize_trace(trace_dir, bench_log, command):
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     out += ["", "bench.py's own per-kernel durations (dispatch-attached events, same workload, "
             "same machine, run without the profiler just before):", ""]
+    if side:
+        for row in bench.get("rows", []):
+            for k, v in row["kernels"].items():
+                out.append(f"- {row['psf']} `{k}`: {v['us']:.2f} us per launch, "
+                           f"HBM fraction {v['hbm_frac']}")
+        return "\n".join(out)
     for k, v in bench.get("kernels", {}).items():
         out.append(f"- `{k}`: {v['avg_us']:.2f} us over {v['launches']} launches")
     rf = bench.get("roofline") or {}
@@ -643,7 +662,7 @@ def summarize_trace(trace_dir, bench_log, command):
     return "\n".join(out)
 
 
-def summarize_pmc(fetch_dir, write_dir, copy_mib, command):
+def summarize_pmc(fetch_dir, write_dir, copy_mib, command, side=0):
     """Per-kernel HBM traffic (KiB per dispatch, averaged) from two rocprofv3 --pmc runs,
     scaled by the ratio of the known size of the calibration copy to what the same
     counter reads for it."""
@@ -677,8 +696,14 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command):
         if name:
             per_launch[name] = round((fa * sf + wa * sw) * 1024.0)
     src_hash = kernel_source_hash()
-    out = ["# HBM traffic counters: phase kernels of the specialised-PSF workload "
-           "(3 x 1024x1024, 20 iterations, batch mode)", "",
+    if side:
+        title = (f"# HBM traffic counters: phase kernels at {side}x{side} (oblique line 31 at "
+                 f"30 deg and disc r=10, two-pass, bench.py --report 7 --sides {side})")
+    else:
+        title = ("# HBM traffic counters: phase kernels of the specialised-PSF workload "
+                 "(3 x 1024x1024, 20 iterations, batch mode)")
+    n_side = side or 1024
+    out = [title, "",
            "Commands (one counter per run; rocprofv3 does not split counters over passes):", "",
            "```", command.strip(), "```", "",
            f"Values are KiB per dispatch, averaged over dispatches.  Calibration: a plain "
@@ -690,8 +715,9 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command):
     for k, n, fa, wa, name in rows:
         out.append(f"| `{k[:90]}` | {n} | {fa:.1f} | {wa:.1f} | "
                    f"{(fa * sf + wa * sw) / 1024:.2f} | {name or ''} |")
-    out += ["", "Algorithmic traffic of one phase launch at 1024 x 1024: 12 B per pixel "
-            "(two float32 planes read, one written) = 12.0 MiB.", "",
+    out += ["", f"Algorithmic traffic of one phase launch at {n_side} x {n_side}: 12 B per "
+            f"pixel (two float32 planes read, one written) = "
+            f"{12.0 * n_side * n_side / 2 ** 20:.1f} MiB.", "",
             "Machine-readable (bench.py reports `bytes_per_launch` as roofline.traffic while "
             "the kernel sources hash to `source_sha256`):", "", "```json",
             json.dumps(dict(source_sha256=src_hash, scale=dict(fetch=sf, write=sw),
@@ -758,7 +784,7 @@ def report_sizes(args, dev):
     rows = []
     for name, h in (("oblique-31-at-30deg", synth.oblique_line(31, 30.0)),
                     ("disc-r10", synth.disc(10))):
-        for side in (512, 1024, 2048, 4096):
+        for side in [int(x) for x in args.sides.split(",")]:
             f = torch.from_numpy(synth.observe(synth.latent_image(side, side, 7), h,
                                                "gaussian", 7)).to(dev)
             j = Job(f, h, path="runs")
