@@ -61,3 +61,31 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def _stats(dirname, rows):
+    os.makedirs(dirname, exist_ok=True)
+    with open(os.path.join(dirname, "bench_kernel_stats.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs",
+                                           "MinNs", "MaxNs", "Percentage"])
+        w.writeheader()
+        for name, calls, avg in rows:
+            w.writerow(dict(Name=name, Calls=calls, TotalDurationNs=calls * avg, AverageNs=avg,
+                            MinNs=avg, MaxNs=avg, Percentage=50.0))
+
+
+def test_summaries_of_a_size_sweep_run(tmp_path):
+    span = "void rlk::span_kernel<0, 8, 8, 8, false>(rlk::LaunchArgs)"
+    _stats(tmp_path / "kt", [(span, 63, 90000.0)])
+    log = tmp_path / "r7.log"
+    log.write_text(json.dumps(dict(report="sweep", rows=[dict(
+        psf="oblique", side=4096, kernels=dict(span_conv_ratio=dict(us=91.0, hbm_frac=0.28)))]))
+        + "\n")
+    text = bench.summarize_trace(str(tmp_path / "kt"), str(log), "cmd", 4096)
+    assert "4096x4096" in text and "| 63 | 5.67 | 90.00 |" in text
+    assert "oblique `span_conv_ratio`: 91.00 us per launch" in text
+    copy = "__amd_rocclr_copyBuffer"
+    _pmc(tmp_path / "f", "FETCH_SIZE", [(copy, 512.0), (span, 1000.0)])
+    _pmc(tmp_path / "w", "WRITE_SIZE", [(copy, 1024.0), (span, 400.0)])
+    text = bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), 1, "cmd", 4096)
+    assert "at 4096 x 4096: 12 B per pixel" in text and "= 192.0 MiB" in text
