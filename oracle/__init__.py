@@ -78,6 +78,11 @@ def _load(mutant=0):
         lib.oracle_below.restype = ctypes.c_int
         lib.oracle_below.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                      ctypes.c_float]
+        lib.oracle_below_many.restype = None
+        lib.oracle_below_many.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float), ctypes.c_long,
+                                          ctypes.c_int, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_tv_div.restype = None
         lib.oracle_tv_div.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
         lib.oracle_rl_tv.restype = None
@@ -195,6 +200,18 @@ class Oracle:
         """float32 convergence decision of Section 4 (ABS or REL threshold)."""
         return bool(self.lib.oracle_below(float(np.float32(a)), float(np.float32(b)),
                                           THIN[mode], float(np.float32(tau))))
+
+    def below_many(self, a, b, mode, tau):
+        """The same decision for every pair of two float32 arrays (bool array)."""
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        assert a.shape == b.shape
+        out = np.empty(a.shape, dtype=np.uint8)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self.lib.oracle_below_many(a.ctypes.data_as(fp), b.ctypes.data_as(fp), a.size,
+                                   THIN[mode], float(np.float32(tau)),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        return out.astype(bool)
 
     def thin_step(self, f, u, r, cnt, h, k, thin, bc="reflect"):
         """One thinned iteration k, in place on u, r (float64) and cnt (uint8).

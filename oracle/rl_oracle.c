@@ -346,14 +346,27 @@ long oracle_thin_step(const double *f, double *u, double *r, uint8_t *cnt, int H
     for (long y = 0; y < H; ++y)
         for (long x = 0; x < W; ++x) {
             long p = y * W + x;
+#if ORACLE_MUTANT == 11
+            /* planted: the ratio of inactive pixels is recomputed instead of kept stale */
+            r[p] = ratio(f[p], conv_at(u_prev, H, W, h, kh, kw, bc, y, x));
+#else
             if (full || cnt[p] < hyst)
                 r[p] = ratio(f[p], conv_at(u_prev, H, W, h, kh, kw, bc, y, x));
+#endif
         }
 #pragma omp parallel for schedule(static)
     for (long y = 0; y < H; ++y)
         for (long x = 0; x < W; ++x) {
             long p = y * W + x;
+#if ORACLE_MUTANT == 10
+            /* planted: frozen pixels are still updated (only their counter is kept) */
+            if (!(full || cnt[p] < hyst)) {
+                u[p] = update(u_prev[p], corr_at(r, H, W, h, kh, kw, bc, y, x));
+                continue;
+            }
+#else
             if (!(full || cnt[p] < hyst)) continue;
+#endif
             double un = update(u_prev[p], corr_at(r, H, W, h, kh, kw, bc, y, x));
             u[p] = un;
             if (mode != THIN_OFF) {
@@ -362,6 +375,13 @@ long oracle_thin_step(const double *f, double *u, double *r, uint8_t *cnt, int H
             }
         }
     return n_active;
+}
+
+/* The convergence test above applied to n pairs (a[i], b[i]); out[i] = 0 or 1. */
+void oracle_below_many(const float *a, const float *b, long n, int mode, float tau,
+                       uint8_t *out)
+{
+    for (long i = 0; i < n; ++i) out[i] = (uint8_t)oracle_below(a[i], b[i], mode, tau);
 }
 
 /* Sum in row-major order (used for the flux sum(u)). */

@@ -204,6 +204,74 @@ def test_below_closed_form(orc):
     assert orc.below(0.5, 0.5, "rel", 1e-4)
 
 
+# ---- thinned step: what frozen pixels keep (Section 4, eq. 4-5) -----------------------------
+def _thin_state(shape, hyst, seed):
+    """A seeded mid-run state: positive u^k and stale r, counters with a block of frozen
+    pixels and scattered frozen ones (cnt >= hyst) among active ones."""
+    rng = np.random.default_rng(seed)
+    H, W = shape
+    u = rng.uniform(0.1, 1.0, shape)
+    r = rng.uniform(0.5, 1.5, shape)
+    f = rng.uniform(0.05, 1.0, shape)
+    frozen = rng.random(shape) < 0.35
+    frozen[H // 4:H // 2, W // 3:2 * W // 3] = True
+    cnt = np.where(frozen, rng.integers(hyst, 60, shape), rng.integers(0, hyst, shape))
+    return f, u, r, cnt.astype(np.uint8)
+
+
+def _thin_step_expected(f, u_prev, r_old, cnt0, h, active, thin, mode):
+    """eq. 4-5 written with scipy: active pixels get a fresh ratio and update, computed with
+    the stale ratio of the frozen neighbours; frozen pixels keep u, r and cnt."""
+    h64 = h.astype(np.float64)
+    v = ndimage.convolve(u_prev, h64, mode=mode)
+    r_mixed = np.where(active, np.where(v > 0, f / np.where(v > 0, v, 1.0), 0.0), r_old)
+    u_new = np.where(active, u_prev * ndimage.correlate(r_mixed, h64, mode=mode), u_prev)
+    a32, b32 = u_new.astype(np.float32), u_prev.astype(np.float32)
+    d = np.abs((a32 - b32).astype(np.float32))
+    t = (np.float32(thin["tau"]) * b32).astype(np.float32) if thin["mode"] == "rel" \
+        else np.float32(thin["tau"])
+    below = (d < t) | ((a32 == 0) & (b32 == 0))
+    cnt = np.where(active, np.where(below, np.minimum(cnt0.astype(int) + 1, 255), 0), cnt0)
+    return u_new, r_mixed, cnt.astype(np.uint8)
+
+
+@pytest.mark.parametrize("bc,mode", [("reflect", "reflect"), ("replicate", "nearest")])
+@pytest.mark.parametrize("k", [13, 20])
+def test_thin_step_frozen_pixels(orc, bc, mode, k):
+    thin = dict(mode="rel", tau=0.06, hysteresis=3, reset_period=10, compact_period=10)
+    for h in (synth.disc(3), synth.oblique_line(9, 30.0), synth.dense_random(5, 3)):
+        f, u0, r0, c0 = _thin_state((41, 37), thin["hysteresis"], 77 + k)
+        full = oracle.is_full(k, thin["reset_period"])
+        active = np.ones(f.shape, bool) if full else c0 < thin["hysteresis"]
+        assert full or 0 < active.sum() < f.size
+        want_u, want_r, want_c = _thin_step_expected(f, u0, r0, c0, h, active, thin, mode)
+        u, r, c = u0.copy(), r0.copy(), c0.copy()
+        n = orc.thin_step(f, u, r, c, h, k, thin, bc)
+        assert n == int(active.sum())
+        # frozen pixels: u, r and counter untouched, bit for bit
+        assert np.array_equal(u[~active], u0[~active])
+        assert np.array_equal(r[~active], r0[~active])
+        assert np.array_equal(c[~active], c0[~active])
+        np.testing.assert_allclose(u, want_u, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(r, want_r, rtol=1e-13, atol=0)
+        # the decisions are far from the threshold at this tau on random data, and both
+        # outcomes occur
+        assert np.array_equal(c, want_c)
+        assert 0 < np.count_nonzero(c[active] == 0) < active.sum()
+
+
+def test_below_many_matches_below(orc):
+    rng = np.random.default_rng(9)
+    b = rng.uniform(0.0, 2.0, 400).astype(np.float32)
+    a = (b * (1 + rng.uniform(-3e-4, 3e-4, 400))).astype(np.float32)
+    a[:5] = 0.0
+    b[:3] = 0.0
+    for mode, tau in (("rel", 1e-4), ("abs", 1e-4), ("rel", 0.0)):
+        got = orc.below_many(a, b, mode, tau)
+        want = [orc.below(x, y, mode, tau) for x, y in zip(a, b)]
+        assert got.tolist() == want
+
+
 def _golden_rows(name):
     rows = []
     with open(os.path.join(GOLDEN, name)) as fh:
@@ -323,6 +391,18 @@ def _pins_pass(o):
         g = (energy(uu + ep) - energy(uu - ep)) / 2e-6
         if not abs((den - num)[5, 6] - g) <= 1e-5 * max(1.0, abs(g)):
             return False
+        # thinned step: frozen pixels keep u and their stale ratio (eq. 4-5)
+        thin = dict(mode="rel", tau=0.06, hysteresis=3, reset_period=10, compact_period=10)
+        hd = synth.disc(2)
+        f, u0, r0, c0 = _thin_state((17, 15), 3, 5)
+        active = c0 < 3
+        want_u, want_r, _ = _thin_step_expected(f, u0, r0, c0, hd, active, thin, "reflect")
+        uu, rr, cc = u0.copy(), r0.copy(), c0.copy()
+        o.thin_step(f, uu, rr, cc, hd, 13, thin)
+        if not (np.array_equal(uu[~active], u0[~active]) and
+                np.array_equal(rr[~active], r0[~active]) and
+                np.allclose(uu, want_u, rtol=1e-13, atol=0)):
+            return False
         e = 2.0 ** -13
         if o.below(1.0 + e, 1.0, "abs", e) or not o.below(1.0 + e, 1.0, "abs", 1.5 * e):
             return False
@@ -335,7 +415,7 @@ def _pins_pass(o):
 
 def test_planted_mistakes_are_caught():
     assert _pins_pass(oracle.Oracle(0))
-    for m in range(1, 10):
+    for m in range(1, 12):
         assert not _pins_pass(oracle.Oracle(m)), f"mutant {m} passed the pins"
 
 
