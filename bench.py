@@ -1,18 +1,29 @@
 """Benchmark: Richardson-Lucy pixel-iterations per second on one MI355X.
 
-Workload (one "step"): the specialised-PSF configuration -- three 1024 x 1024 float32
-images from the seeded generator, Gaussian noise sigma 0.01, 200 RL iterations each:
-  (a) vertical motion blur, box of length 41      -> BOX_AXIS path
-  (b) oblique motion line, length 31 at 30 deg, antialiased -> RUNS path (row spans)
-  (c) uniform disc of radius 10                   -> RUNS path (sliding runs)
-A step runs all three jobs end to end through the C ABI: rl_init for each (copy f into
-the workspace, upload the compiled PSF), one rl_iterate_batch call that advances all
-three by 200 iterations (independent kernel groups on concurrent streams), and rl_result
-for each (copy u^K out).  Inputs are resident on the GPU before the timed region starts.
---mode sequential runs rl_iterate per job instead (the plain per-image method).
+Default workload (one "step"): the batched configuration -- 256 float32 images from the
+seeded generator, sides drawn log-uniformly in 256..2048 (non-square), each with a PSF
+drawn uniformly from {axis-aligned motion box of length 5-63, antialiased oblique motion
+line of length 9-47 at a uniform angle, uniform disc of radius 3-24, dense 15 x 15
+random}, Poisson noise at peak 255, 100-300 RL iterations each, compensated float32 sums.
+A step runs every job end to end through the C ABI: rl_init for each (copy f into its
+workspace, upload the compiled PSF), ONE rl_iterate_batch call that advances all of them
+by their own iteration counts, and rl_result for each (copy u^K out).  Inputs are
+resident on the GPU before the timed region starts.
 
-Prints ONE JSON line.  Options: --gpus (must be 1), --steps, --warmup, --no-cpu-baseline,
---no-kernel-timing, --mode, --compare.
+The line's `accuracy` compares the outputs of the last timed step of the two cheapest
+jobs of each PSF class with full-length FP64 oracle runs (the same runs time the CPU
+baseline).  `roofline` belongs to the kernel with the largest total time, charged
+12 B per pixel-iteration (6 B per output of each of the two phase launches of an
+iteration), or its algorithmic flops where those bind.
+
+--workload specialised times the specialised-PSF configuration instead: three 1024 x 1024
+images (vertical box 41 -> BOX_AXIS, oblique line 31 at 30 deg -> RUNS spans, disc r=10 ->
+RUNS sliding runs), Gaussian noise sigma 0.01, 200 iterations each, all three checked
+against the oracle at full length.  --mode sequential runs rl_iterate per job instead of
+one batch call (the plain per-image method).
+
+Prints ONE JSON line.  Options: --gpus (must be 1), --steps, --warmup, --workload,
+--no-cpu-baseline, --no-kernel-timing, --no-kahan, --mode, --compare.
 
 --report N prints, instead of the benchmark line, one JSON report line for another
 configuration:
@@ -51,18 +62,25 @@ import numpy as np  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 # FP32 vector peak of MI355X: 256 CUs x 128 FP32 lanes (packed) x 2 flops (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
+# the same without packed FP32 instructions (switched off in this build): 64 lanes per CU
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Algorithmic HBM bytes per output of one phase kernel: phase A reads u^k and f and writes
-# r; phase B reads r and u^k and writes u^{k+1} (float32 each).  Halo re-reads are not
-# algorithmic.  The resident box solver reads u and f and writes u once per launch.
-BYTES_PER_PX_PHASE = 12.0
+# Algorithmic HBM bytes of one RL iteration on one pixel: u^k and f read, u^{k+1} written
+# (float32 each); v and the ratio need not leave the chip.  A two-pass iteration is
+# charged half of it per phase launch (BYTES_PER_PX_PHASE); halo re-reads and the ratio's
+# round trip through HBM are not algorithmic.
+BYTES_PER_PX_IT = 12.0
+BYTES_PER_PX_PHASE = BYTES_PER_PX_IT / 2
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "phase-kernels-1024_traffic.md")
+TRAFFIC_PROFILES = {
+    "batched": os.path.join(ROOT, "profiles", "batched-256_traffic.md"),
+    "specialised": os.path.join(ROOT, "profiles", "phase-kernels-1024_traffic.md"),
+}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_7211_amd", "csrc", n)
                   for n in ("rl_kernels.hpp", "rl_api.hip", "psf_compile.cpp", "psf_compile.hpp")]
 
@@ -76,12 +94,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(name):
+def measured_traffic(name, workload="batched"):
     """HBM bytes per launch of kernel `name` (timing-registry name) from the committed
-    rocprofv3 counter summary, or None if there is none or the kernel sources changed
-    since the counters were taken."""
+    rocprofv3 counter summary of the workload, or None if there is none or the kernel
+    sources changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILES[workload]).read()
     except OSError:
         return None
     a = text.find("```json")
@@ -113,14 +131,118 @@ def algorithmic_flops_per_px(kind, info, phase_b):
     return conv + 1.0
 
 
+def job_kind(A, inf):
+    """Kernel family of a job from its description (rl_job_describe)."""
+    if inf["schedule"] == A.RL_SCHED_RESIDENT:
+        return "resident"
+    if inf["path"] == A.RL_PATH_BOX_RECT:
+        return "rect"
+    if inf["path"] == A.RL_PATH_BOX_SAT:
+        return "sat"
+    return "slide" if inf["lmax"] == 0 else ("direct" if inf["lmax"] == 1 else "span")
+
+
+def kernel_work(A, jobs, infos):
+    """Algorithmic bytes and flops of every timing-registry kernel over one step.
+
+    A phase launch of a job with n pixels moves 6 B per pixel: one RL iteration moves
+    12 B per pixel-iteration (u^k and f read, u^{k+1} written; the ratio needs no HBM
+    round trip in principle), and the two-pass schedule splits each iteration into two
+    launches, so each is charged half.  The resident solver runs all K iterations of a
+    job in one launch: 12 B x n x K.  Flops: algorithmic_flops_per_px per output of
+    each launch."""
+    work = {}
+    for j in jobs:
+        inf = infos[j["name"]]
+        kind = job_kind(A, inf)
+        units = j["f"].size * j["iters"]
+        if kind == "resident":
+            names = [("resident_box", BYTES_PER_PX_IT, False)]
+        else:
+            names = [(f"{kind}_conv_ratio", BYTES_PER_PX_IT / 2, False),
+                     (f"{kind}_corr_update", BYTES_PER_PX_IT / 2, True)]
+        for nm, bpp, phase_b in names:
+            w = work.setdefault(nm, dict(bytes=0.0, flops=0.0, jobs=[], px_it=0))
+            w["bytes"] += bpp * units
+            w["flops"] += algorithmic_flops_per_px(kind, inf, phase_b) * units
+            w["px_it"] += units
+            w["jobs"].append(j["name"])
+    return work
+
+
+def roofline_of(kernels, work, traffic_fn):
+    """Roofline object of the kernel with the largest total time: the bound is the
+    resource whose peak gives the longer minimum time for its algorithmic work."""
+    if not kernels:
+        return None
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    kinfo, w = kernels[dom], work.get(dom)
+    if not w:
+        return None
+    t = kinfo["total_ms"] * 1e-3
+    n = kinfo["launches"]
+    by, fl = w["bytes"] / n, w["flops"] / n  # per launch
+    dt = kinfo["avg_us"] * 1e-6
+    t_alu = fl / (PEAK_FP32_TFLOPS * 1e12)
+    t_hbm = by / (PEAK_HBM_GBS * 1e9)
+    tr = traffic_fn(dom)
+    hbm = by / dt / 1e9
+    alu = fl / dt / 1e12
+    if t_hbm >= t_alu:
+        rf = dict(bound="hbm", achieved=round(hbm, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                  frac=round(hbm / PEAK_HBM_GBS, 5), traffic=tr)
+    else:
+        rf = dict(bound="alu", achieved=round(alu, 4), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                  frac=round(alu / PEAK_FP32_TFLOPS, 5), traffic=tr)
+    rf.update(kernel=dom, launches=n, avg_us=round(kinfo["avg_us"], 3),
+              total_ms=round(kinfo["total_ms"], 3),
+              jobs=len(w["jobs"]), bytes_per_launch=round(by), flops_per_launch=round(fl),
+              hbm_frac=round(hbm / PEAK_HBM_GBS, 5),
+              alu_frac=round(alu / PEAK_FP32_TFLOPS, 5),
+              alu_frac_unpacked=round(alu / PEAK_FP32_UNPACKED_TFLOPS, 5),
+              px_it_per_s=round(w["px_it"] / t))
+    return rf
+
+
+KERNEL_NAMES = ["resident_box", "rect_conv_ratio", "rect_corr_update", "sat_conv_ratio",
+                "sat_corr_update", "slide_conv_ratio", "slide_corr_update", "span_conv_ratio",
+                "span_corr_update", "direct_conv_ratio", "direct_corr_update"]
+
+
+def read_kernel_timing(A):
+    kernels = {}
+    for nm in KERNEL_NAMES:
+        n, ms = A.rl_timing_read(nm)
+        if n:
+            kernels[nm] = dict(launches=n, total_ms=ms, avg_us=1e3 * ms / n)
+    return kernels
+
+
+def checked_jobs(jobs, per_class=2):
+    """Indices of the `per_class` cheapest jobs (pixels x iterations x taps) of each PSF
+    class of the batched workload: the jobs whose full-length results the FP64 oracle
+    checks."""
+    cls = {}
+    for i, j in enumerate(jobs):
+        c = j["name"].split("-")[1]
+        cost = j["f"].size * j["iters"] * np.count_nonzero(j["psf"])
+        cls.setdefault(c, []).append((cost, i))
+    return [i for c in sorted(cls) for _, i in sorted(cls[c])[:per_class]]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["batched", "specialised"], default="batched",
+                    help="batched: 256 uneven images with mixed PSFs (the default); "
+                         "specialised: three 1024x1024 images with the specialised PSFs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--no-kahan", action="store_true",
+                    help="batched workload: plain float32 sums instead of compensated ones")
+    ap.add_argument("--iters", type=int, default=200, help="specialised workload: iterations")
     ap.add_argument("--mode", choices=["batch", "sequential"], default="batch")
     ap.add_argument("--compare", action="store_true",
                     help="also time the other mode (reported as 'other_mode')")
@@ -131,6 +253,8 @@ def main():
     ap.add_argument("--summary-side", type=int, default=0,
                     help="--summarize-pmc / --summarize-trace: the profiled run was "
                          "--report 7 --sides N with this N (default: the benchmark workload)")
+    ap.add_argument("--summary-workload", choices=["batched", "specialised"], default="batched",
+                    help="--summarize-pmc / --summarize-trace: workload of the profiled run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the "
                          "reference dispatch for scaling HBM counters)")
@@ -148,11 +272,12 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
-                            args.calibrate_copy, args.pmc_command, args.summary_side))
+                            args.calibrate_copy, args.pmc_command, args.summary_side,
+                            args.summary_workload))
         return
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace[0], args.summarize_trace[1],
-                              args.pmc_command, args.summary_side))
+                              args.pmc_command, args.summary_side, args.summary_workload))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -160,9 +285,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import synth
+    jobs = None
+    if args.report is None and args.workload == "batched":
+        # images first, in forked workers, before anything touches the GPU
+        t0 = time.perf_counter()
+        workers = max(1, min(16, os.cpu_count() or 1))
+        jobs = synth.job_for_config(4, workers=workers, pool="fork")
+        log(f"bench: {len(jobs)} batched jobs generated in {time.perf_counter() - t0:.1f}s "
+            f"({workers} workers)")
+
     import torch
 
-    import synth
     from paper_1304_7211_amd import _abi as A
     from paper_1304_7211_amd.job import BatchRunner, Job
 
@@ -181,10 +315,14 @@ def main():
                 5: report_serving, 6: report_rect, 7: report_sizes}[args.report](args, dev)
         print(json.dumps(line), flush=True)
         return
-    jobs = synth.job_for_config(2)
-    for j in jobs:
-        j["iters"] = args.iters
-    log(f"bench: {len(jobs)} jobs, {[j['name'] for j in jobs]}, iters={args.iters}")
+    batched = args.workload == "batched"
+    kahan = not args.no_kahan
+    if not batched:
+        jobs = synth.job_for_config(2)
+        for j in jobs:
+            j["iters"] = args.iters
+    log(f"bench: {len(jobs)} jobs, iters {min(j['iters'] for j in jobs)}.."
+        f"{max(j['iters'] for j in jobs)}, workload {args.workload}")
     f_dev = [torch.from_numpy(j["f"]).to(dev) for j in jobs]
     outs = [torch.empty_like(f) for f in f_dev]
     torch.cuda.synchronize()
@@ -193,16 +331,19 @@ def main():
     infos = {}
     runner = BatchRunner(len(jobs))
 
+    def new_job(j, f):
+        return Job(f, j["psf"], path=j["path"], kahan=kahan)
+
     def step_sequential():
         for j, f, o in zip(jobs, f_dev, outs):
-            job = Job(f, j["psf"], path=j["path"])
+            job = new_job(j, f)
             job.iterate(j["iters"])
             job.result(out=o)
             infos[j["name"]] = job.describe()
             job.close()
 
     def step_batch():
-        js = [Job(f, j["psf"], path=j["path"]) for j, f in zip(jobs, f_dev)]
+        js = [new_job(j, f) for j, f in zip(jobs, f_dev)]
         runner.iterate(js, [j["iters"] for j in jobs])
         for j, jb, o in zip(jobs, js, outs):
             jb.result(out=o)
@@ -227,6 +368,9 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = px_it_step * args.steps / elapsed
     log(f"bench: {args.steps} steps in {elapsed:.4f}s -> {value:.4g} px-it/s ({args.mode})")
+    # the outputs of the last timed step, for the accuracy check against the FP64 oracle
+    picked = checked_jobs(jobs) if batched else list(range(len(jobs)))
+    timed_out = {i: outs[i].cpu().numpy() for i in picked}
     other = None
     if args.compare:
         ostep = step_sequential if args.mode == "batch" else step_batch
@@ -242,78 +386,59 @@ def main():
                      ms_per_step=1e3 * (o1 - o0) / args.steps)
         log(f"bench: other mode {other}")
 
-    # per-kernel durations: the same steps again with every launch bracketed by HIP events
-    # on the stream it is launched on (events add a few microseconds per launch, so the
-    # headline value above comes from the uninstrumented run)
+    # per-kernel durations: one more step with every launch carrying HIP events in its
+    # dispatch packet, on the stream it is launched on (the events add a little time per
+    # launch, so the headline value above comes from the uninstrumented run)
     roofline = None
     kernels = {}
-    kt = not args.no_kernel_timing
-    if kt:
+    if not args.no_kernel_timing:
         A.rl_timing_reset()
         A.rl_timing_enable(True)
         torch.cuda.synchronize()
-        for s in range(args.steps):
-            step()
+        step()
         torch.cuda.synchronize()
         A.rl_timing_enable(False)
-        names = ["resident_box", "mixed_conv_ratio", "mixed_corr_update", "rect_conv_ratio",
-                 "rect_corr_update", "slide_conv_ratio",
-                 "slide_corr_update", "span_conv_ratio",
-                 "span_corr_update", "direct_conv_ratio", "direct_corr_update"]
-        for nm in names:
-            n, ms = A.rl_timing_read(nm)
-            if n:
-                kernels[nm] = dict(launches=n, total_ms=ms, avg_us=1e3 * ms / n)
+        kernels = read_kernel_timing(A)
         A.rl_timing_reset()
-        if kernels:
-            dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-            kinfo = kernels[dom]
-            kind = dom.split("_")[0]
-            # the jobs the dominant kernel ran (a mixed launch covers span and sliding jobs)
-            def job_kind(inf):
-                if inf["schedule"] == A.RL_SCHED_RESIDENT:
-                    return "resident"
-                if inf["path"] == A.RL_PATH_BOX_RECT:
-                    return "rect"
-                if inf["path"] == A.RL_PATH_BOX_SAT:
-                    return "sat"
-                return "slide" if inf["lmax"] == 0 else ("direct" if inf["lmax"] == 1 else "span")
-            covered = [j for j in jobs
-                       if (job_kind(infos[j["name"]]) == kind
-                           or (kind == "mixed" and job_kind(infos[j["name"]]) in ("span", "slide", "direct")))]
-            jname = "+".join(j["name"] for j in covered)
-            fl = by = 0.0
-            for jj in covered:
-                inf = infos[jj["name"]]
-                npx = jj["f"].size
-                units = npx * jj["iters"] if kind == "resident" else npx
-                fl += algorithmic_flops_per_px(job_kind(inf), inf, dom.endswith("update")) * units
-                by += BYTES_PER_PX_PHASE * npx
-            # roofline: the bound is the resource whose peak gives the longer minimum time
-            t_alu = fl / (PEAK_FP32_TFLOPS * 1e12)
-            t_hbm = by / (PEAK_HBM_GBS * 1e9)
-            dt = kinfo["avg_us"] * 1e-6
-            tr = measured_traffic(dom)
-            if t_hbm >= t_alu:
-                achieved = by / dt / 1e9
-                roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS,
-                                unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 5),
-                                traffic=tr)
-            else:
-                achieved = fl / dt / 1e12
-                roofline = dict(bound="alu", achieved=round(achieved, 4),
-                                peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                                frac=round(achieved / PEAK_FP32_TFLOPS, 5), traffic=tr)
-            roofline.update(kernel=dom, job=jname, avg_us=round(kinfo["avg_us"], 3),
-                            bytes_per_launch=by, flops_per_launch=fl,
-                            alu_frac=round(fl / dt / 1e12 / PEAK_FP32_TFLOPS, 5),
-                            hbm_frac=round(by / dt / 1e9 / PEAK_HBM_GBS, 5))
+        work = kernel_work(A, jobs, infos)
+        for nm, k in kernels.items():
+            w = work.get(nm)
+            if w:
+                dt = k["total_ms"] * 1e-3
+                k.update(hbm_frac=round(w["bytes"] / dt / 1e9 / PEAK_HBM_GBS, 5),
+                         alu_frac=round(w["flops"] / dt / 1e12 / PEAK_FP32_TFLOPS, 5),
+                         jobs=len(w["jobs"]))
+        roofline = roofline_of(kernels, work,
+                               lambda nm: measured_traffic(nm, args.workload))
     log(f"bench: kernels {json.dumps(kernels)}")
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(jobs)
+        cpu, accuracy = cpu_baseline(jobs, picked, timed_out, full_length=batched)
 
+    if batched:
+        cls = {}
+        for j in jobs:
+            c = j["name"].split("-")[1]
+            cls[c] = cls.get(c, 0) + 1
+        config = {"workload": "batched: 256 images, sides log-uniform 256..2048 (seeded, "
+                              "non-square), PSFs uniform over {axis box 5-63, oblique line "
+                              "9-47 at a uniform angle, disc r 3-24, dense 15x15}, 100-300 "
+                              "iterations, Poisson peak 255, one rl_iterate_batch call",
+                  "jobs": len(jobs), "psf_classes": cls, "kahan": kahan,
+                  "mode": args.mode, "px_it_per_step": px_it_step}
+        data = "synthetic (seeded generator: shapes + sinusoid, reflect blur, Poisson noise)"
+    else:
+        config = {"workload": "specialised PSFs 1024x1024 x3 (vertical box 41, oblique "
+                              f"31@30deg AA, disc r10), {args.iters} iterations each",
+                  "mode": args.mode, "px_it_per_step": px_it_step}
+        data = "synthetic (seeded generator: shapes + sinusoid, reflect blur, Gaussian noise)"
+    paths = {}
+    for v in infos.values():
+        key = f"{A.PATH_NAMES[v['path']]}/{A.SCHED_NAMES[v['schedule']]}"
+        paths[key] = paths.get(key, 0) + 1
+    config["paths"] = paths
     line = {
         "metric": "RL pixel-iterations/s at <=1e-5 rel err vs FP64",
         "value": value,
@@ -326,15 +451,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded generator: shapes + sinusoid, reflect blur, Gaussian noise)",
-        "config": {"workload": "specialised PSFs 1024x1024 x3 (vertical box 41, oblique 31@30deg AA, "
-                               "disc r10), 200 iterations each",
-                   "mode": args.mode,
-                   "px_it_per_step": px_it_step,
-                   "paths": {k: {"path": A.PATH_NAMES[v["path"]],
-                                 "schedule": A.SCHED_NAMES[v["schedule"]]}
-                             for k, v in infos.items()}},
+        "data": data,
+        "config": config,
         "roofline": roofline,
+        # the whole step's pixel-iterations at the algorithmic 12 B each, against HBM
+        "method_hbm_frac": round(value * BYTES_PER_PX_IT / (PEAK_HBM_GBS * 1e9), 5),
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
         "kernels": kernels,
         "other_mode": other,
@@ -452,7 +574,7 @@ def report_batched(args, dev):
     import synth
     from paper_1304_7211_amd.job import BatchRunner, Job
     t0 = time.perf_counter()
-    jobs = synth.job_for_config(4)
+    jobs = synth.job_for_config(4, workers=max(1, min(16, os.cpu_count() or 1)))
     log(f"report 4: {len(jobs)} jobs generated in {time.perf_counter() - t0:.1f}s")
     fs = [torch.from_numpy(j["f"]).to(dev) for j in jobs]
     px_it = sum(j["f"].size * j["iters"] for j in jobs)
@@ -476,12 +598,7 @@ def report_batched(args, dev):
             jb.close()
         log(f"report 4: kahan={kahan} {dt * 1e3:.1f} ms, {px_it / dt:.3g} px-it/s")
     # FP64 oracle on the two cheapest jobs of each PSF class
-    cls = {}
-    for i, j in enumerate(jobs):
-        c = j["name"].split("-")[1]
-        cost = j["f"].size * j["iters"] * np.count_nonzero(j["psf"])
-        cls.setdefault(c, []).append((cost, i))
-    picked = [i for c in sorted(cls) for _, i in sorted(cls[c])[:2]]
+    picked = checked_jobs(jobs)
     o = oracle.Oracle()
     errs = []
     for i in picked:
@@ -617,7 +734,21 @@ def _timing_name(kernel):
     return f"{kind}_{'corr_update' if phase_b else 'conv_ratio'}"
 
 
-def summarize_trace(trace_dir, bench_log, command, side=0):
+def _registry_totals(rows):
+    """Sum (calls, total ns) per timing-registry name over the kernel symbols of a
+    rocprofv3 kernel-statistics table (several template instances share one name)."""
+    agg = {}
+    for r in rows:
+        nm = _timing_name(r["Name"])
+        if not nm:
+            continue
+        a = agg.setdefault(nm, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+    return agg
+
+
+def summarize_trace(trace_dir, bench_log, command, side=0, workload="batched"):
     """Per-kernel durations from rocprofv3's kernel statistics, next to bench.py's own
     dispatch-event durations of an unprofiled run of the same workload (the benchmark, or
     with side > 0 the size sweep of --report 7 at that side)."""
@@ -632,11 +763,17 @@ def summarize_trace(trace_dir, bench_log, command, side=0):
                  f"and disc r=10, two-pass, bench.py --report 7 --sides {side})")
         note = ("The run covers the report's warmup, timed and instrumented iterations of "
                 "both PSFs.")
+    elif workload == "batched":
+        title = ("# Kernel trace: bench.py default workload (batched: 256 uneven images, "
+                 "mixed PSFs, 100-300 iterations, one rl_iterate_batch call per step)")
+        note = ("The run covers bench.py's warmup step, its timed steps and its instrumented "
+                "step. rocprofv3 lengthens the uninstrumented timing, so the headline value "
+                "comes from runs without the profiler.")
     else:
-        title = ("# Kernel trace: bench.py default workload (specialised PSFs, 3 x 1024x1024, "
+        title = ("# Kernel trace: bench.py --workload specialised (3 x 1024x1024, "
                  "200 iterations, batch mode)")
         note = ("The run covers bench.py's warmup step, its timed steps and its instrumented "
-                "steps. rocprofv3 lengthens the uninstrumented timing, so the headline value "
+                "step. rocprofv3 lengthens the uninstrumented timing, so the headline value "
                 "comes from runs without the profiler.")
     out = [title, "", "Command:", "", "```", command.strip(), "```", "", note, "",
            "| Kernel | calls | total ms | avg us | min us | max us | % |",
@@ -645,6 +782,13 @@ def summarize_trace(trace_dir, bench_log, command, side=0):
         out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    agg = _registry_totals(rows)
+    if agg:
+        out += ["", "The same, summed per timing-registry name (the names bench.py reports):",
+                "", "| Registry name | calls | total ms | avg us |", "|---|---|---|---|"]
+        for nm in sorted(agg, key=lambda k: -agg[k][1]):
+            c, ns = agg[nm]
+            out.append(f"| `{nm}` | {c} | {ns / 1e6:.2f} | {ns / c / 1e3:.2f} |")
     out += ["", "bench.py's own per-kernel durations (dispatch-attached events, same workload, "
             "same machine, run without the profiler just before):", ""]
     if side:
@@ -658,17 +802,18 @@ def summarize_trace(trace_dir, bench_log, command, side=0):
     rf = bench.get("roofline") or {}
     out += ["", f"Headline of that run: {bench['value']:.4g} {bench['unit']}, "
             f"{bench['ms_per_step']:.3f} ms per step; roofline of `{rf.get('kernel')}`: "
-            f"{rf.get('achieved')} {rf.get('unit')} = {rf.get('frac')} of {rf.get('peak')}."]
+            f"{rf.get('achieved')} {rf.get('unit')} = {rf.get('frac')} of {rf.get('peak')} "
+            f"(bound {rf.get('bound')})."]
     return "\n".join(out)
 
 
-def summarize_pmc(fetch_dir, write_dir, copy_mib, command, side=0):
+def summarize_pmc(fetch_dir, write_dir, copy_mib, command, side=0, workload="batched"):
     """Per-kernel HBM traffic (KiB per dispatch, averaged) from two rocprofv3 --pmc runs,
     scaled by the ratio of the known size of the calibration copy to what the same
-    counter reads for it."""
+    counter reads for it.  Dispatches of kernel symbols that share a timing-registry name
+    are pooled: bytes_per_launch is their scaled total over their count."""
     import csv
     import glob
-    import hashlib
 
     def read(d, counter):
         fn = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
@@ -687,22 +832,27 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command, side=0):
     cal = max(others, key=lambda k: max(fetch[k]))
     f_cal, w_cal = max(fetch[cal]), max(write[cal])
     sf, sw = known / f_cal, known / w_cal
-    rows, per_launch = [], {}
+    rows, pooled = [], {}
     for k in sorted(set(fetch) | set(write)):
         fv, wv = fetch.get(k, [0.0]), write.get(k, [0.0])
         fa, wa = sum(fv) / len(fv), sum(wv) / len(wv)
         name = _timing_name(k)
         rows.append((k, len(fv), fa, wa, name))
         if name:
-            per_launch[name] = round((fa * sf + wa * sw) * 1024.0)
+            p = pooled.setdefault(name, [0, 0.0])
+            p[0] += len(fv)
+            p[1] += (sum(fv) * sf + sum(wv) * sw) * 1024.0
+    per_launch = {nm: round(tot / n) for nm, (n, tot) in pooled.items()}
     src_hash = kernel_source_hash()
     if side:
         title = (f"# HBM traffic counters: phase kernels at {side}x{side} (oblique line 31 at "
                  f"30 deg and disc r=10, two-pass, bench.py --report 7 --sides {side})")
+    elif workload == "batched":
+        title = ("# HBM traffic counters: kernels of the batched workload (256 uneven images, "
+                 "mixed PSFs, one rl_iterate_batch call)")
     else:
         title = ("# HBM traffic counters: phase kernels of the specialised-PSF workload "
-                 "(3 x 1024x1024, 20 iterations, batch mode)")
-    n_side = side or 1024
+                 "(3 x 1024x1024, batch mode)")
     out = [title, "",
            "Commands (one counter per run; rocprofv3 does not split counters over passes):", "",
            "```", command.strip(), "```", "",
@@ -715,10 +865,16 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command, side=0):
     for k, n, fa, wa, name in rows:
         out.append(f"| `{k[:90]}` | {n} | {fa:.1f} | {wa:.1f} | "
                    f"{(fa * sf + wa * sw) / 1024:.2f} | {name or ''} |")
-    out += ["", f"Algorithmic traffic of one phase launch at {n_side} x {n_side}: 12 B per "
-            f"pixel (two float32 planes read, one written) = "
-            f"{12.0 * n_side * n_side / 2 ** 20:.1f} MiB.", "",
-            "Machine-readable (bench.py reports `bytes_per_launch` as roofline.traffic while "
+    if side:
+        n_side = side
+        out += ["", f"Algorithmic traffic of one phase launch at {n_side} x {n_side}: "
+                f"{BYTES_PER_PX_PHASE:g} B per pixel (half of the {BYTES_PER_PX_IT:g} B of "
+                f"one iteration: u^k and f read, u^(k+1) written) = "
+                f"{BYTES_PER_PX_PHASE * n_side * n_side / 2 ** 20:.1f} MiB."]
+    else:
+        out += ["", f"Algorithmic traffic: {BYTES_PER_PX_PHASE:g} B per output pixel of a "
+                f"phase launch (half of the {BYTES_PER_PX_IT:g} B of one RL iteration)."]
+    out += ["", "Machine-readable (bench.py reports `bytes_per_launch` as roofline.traffic while "
             "the kernel sources hash to `source_sha256`):", "", "```json",
             json.dumps(dict(source_sha256=src_hash, scale=dict(fetch=sf, write=sw),
                             bytes_per_launch=per_launch), indent=1), "```"]
@@ -820,27 +976,72 @@ def report_sizes(args, dev):
             "peak_hbm_gbs": PEAK_HBM_GBS, "rows": rows}
 
 
-def cpu_baseline(jobs):
-    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def rel_err_stats(got, ref, floor=1e-4):
+    """max and 99.9th percentile of |got - ref| / max(|ref|, floor) over the pixels."""
+    e = np.abs(np.asarray(got, np.float64) - ref) / np.maximum(np.abs(ref), floor)
+    return float(e.max()), float(np.quantile(e, 0.999))
+
+
+def cpu_baseline(jobs, picked, timed_out, full_length=True):
+    """The FP64 oracle on the host cores: the full-length runs of the checked jobs, timed
+    (all threads), each compared with the GPU output of the last timed step; then a
+    single-thread rate on a bounded sample of the cheapest checked job."""
     import oracle
     o = oracle.Oracle()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = o.threads()
     total_px_it = 0
+    errs = []
     t0 = time.perf_counter()
-    sample = []
-    for j in jobs:
-        # about 5 s per job: iterations sized by a one-iteration probe
-        p0 = time.perf_counter()
-        o.rl(j["f"], j["psf"], 1)
-        one = max(time.perf_counter() - p0, 1e-3)
-        k = max(1, int(5.0 / one))
-        o.rl(j["f"], j["psf"], k)
-        total_px_it += j["f"].size * (k + 1)
-        sample.append(f"{j['name']} x{k + 1} it")
+    for i in picked:
+        j = jobs[i]
+        ref = o.rl(j["f"], j["psf"], j["iters"])
+        total_px_it += j["f"].size * j["iters"]
+        mx, p999 = rel_err_stats(timed_out[i], ref)
+        errs.append(dict(job=j["name"], shape=list(j["f"].shape), iters=j["iters"],
+                         taps=int(np.count_nonzero(j["psf"])), max_rel_err=mx,
+                         p999_rel_err=p999))
+        log(f"bench: oracle {errs[-1]}")
     dt = time.perf_counter() - t0
     log(f"bench: cpu oracle {total_px_it} px-it in {dt:.2f}s on {cores} threads")
-    return dict(value=total_px_it / dt, unit="px-it/s", cores=cores, kind="oracle",
-                sample="1024x1024, " + ", ".join(sample) + f" ({dt:.1f}s)")
+    # single thread: the cheapest checked job, iterations sized to about 3 s
+    j1 = jobs[min(picked, key=lambda i: jobs[i]["f"].size * np.count_nonzero(jobs[i]["psf"]))]
+    o.set_threads(1)
+    try:
+        p0 = time.perf_counter()
+        o.rl(j1["f"], j1["psf"], 1)
+        one = max(time.perf_counter() - p0, 1e-4)
+        k1 = max(1, min(j1["iters"], int(3.0 / one)))
+        p0 = time.perf_counter()
+        o.rl(j1["f"], j1["psf"], k1)
+        dt1 = time.perf_counter() - p0
+    finally:
+        o.set_threads(cores)
+    single = j1["f"].size * k1 / dt1
+    log(f"bench: cpu oracle single thread {single:.4g} px-it/s ({j1['name']} x{k1} it)")
+    cpu = dict(value=total_px_it / dt, unit="px-it/s", cores=cores, kind="oracle",
+               sample=f"full-length FP64 oracle runs of {len(picked)} jobs of the workload "
+                      f"({', '.join(e['job'] for e in errs)}; {total_px_it:.3g} px-it in "
+                      f"{dt:.1f}s)",
+               single_core=dict(value=single, unit="px-it/s",
+                                sample=f"{j1['name']} {j1['f'].shape[0]}x{j1['f'].shape[1]}, "
+                                       f"{k1} iterations in {dt1:.1f}s"),
+               cpu_model=cpu_model())
+    worst = max(errs, key=lambda e: e["max_rel_err"])
+    accuracy = dict(metric="max over pixels of |gpu - fp64| / max(|fp64|, 1e-4)",
+                    checked_jobs=len(errs), max_rel_err=worst["max_rel_err"],
+                    worst_job=worst["job"], gate=1e-5,
+                    within_gate=bool(worst["max_rel_err"] <= 1e-5), per_job=errs)
+    return cpu, accuracy
 
 
 if __name__ == "__main__":

@@ -101,6 +101,10 @@ def _load(mutant=0):
                                             ctypes.c_double, dp, dp, dp, dp]
         lib.oracle_sum.restype = ctypes.c_double
         lib.oracle_sum.argtypes = [dp, ctypes.c_long]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
         _libs[mutant] = lib
         return lib
 
@@ -250,6 +254,14 @@ class Oracle:
                 callback(k, u, r, cnt)
         return dict(u=u, r=r, cnt=cnt, active=np.array(active, dtype=np.int64),
                     flux=np.array(flux), lists=lists)
+
+    def threads(self):
+        """Threads the row loops use (OpenMP's current maximum)."""
+        return int(self.lib.oracle_threads())
+
+    def set_threads(self, n):
+        """Thread count of the row loops; the results do not depend on it."""
+        self.lib.oracle_set_threads(int(n))
 
     def sum(self, a):
         a, ap = self._d(a)

@@ -29,7 +29,7 @@
  * Sums run over i ascending, then j ascending; zero taps are skipped (exact).
  * r = f / v where v > 0, else 0 (the paper does not say what happens at v = 0).
  *
- * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (see build_oracle.py).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (build() in __init__.py).
  * -ffp-contract=off keeps every product and sum a separately rounded FP64 operation.
  * OpenMP only splits the image rows among threads; every pixel's sum is computed by one
  * thread in the order above, so the result does not depend on the thread count.
@@ -393,3 +393,13 @@ double oracle_sum(const double *a, long n)
 }
 
 int oracle_mutant(void) { return ORACLE_MUTANT; }
+
+/* Thread count of the row loops (timing only: results do not depend on it). */
+#ifdef _OPENMP
+#include <omp.h>
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_threads(void) { return omp_get_max_threads(); }
+#else
+void oracle_set_threads(int n) { (void)n; }
+int oracle_threads(void) { return 1; }
+#endif

@@ -53,8 +53,9 @@ def log_uniform_side(rng, lo, hi):
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 
 
-def job_for_config(cfg, variant=None, scale=1):
-    """Jobs of configuration ``cfg``.  ``scale`` > 1 shrinks image sides (tests only)."""
+def job_for_config(cfg, variant=None, scale=1, workers=1, pool="thread"):
+    """Jobs of configuration ``cfg``.  ``scale`` > 1 shrinks image sides (tests only);
+    ``workers`` and ``pool`` parallelise the batched workload's images (see make_jobs)."""
     c = CONFIGS[cfg]
     if cfg == 1:
         return [make_job(c["name"], c["H"] // scale, c["W"] // scale, P.box_h(15), c["K"],
@@ -72,14 +73,41 @@ def job_for_config(cfg, variant=None, scale=1):
                          c["seed"], noise="poisson", peak=c["peak"], path="runs",
                          thin=dict(c["thin"]))]
     if cfg == 4:
-        rng = np.random.default_rng(c["seed"])
-        jobs = []
-        for i in range(c["n_jobs"]):
-            H = max(16, log_uniform_side(rng, c["side_lo"], c["side_hi"]) // scale)
-            W = max(16, log_uniform_side(rng, c["side_lo"], c["side_hi"]) // scale)
-            cls, h = random_psf(rng)
-            K = int(rng.integers(c["K_lo"], c["K_hi"] + 1))
-            jobs.append(make_job(f"b{i}-{cls}", H, W, h, K, 1000 + i, noise="poisson",
-                                 peak=c["peak"]))
-        return jobs
+        return make_jobs(batched_specs(scale), workers=workers, pool=pool)
     raise ValueError(cfg)
+
+
+def batched_specs(scale=1):
+    """Parameters of the batched workload's jobs, drawn in order from one seeded stream;
+    each image then comes from its own seed, so the images can be made in any order."""
+    c = CONFIGS[4]
+    rng = np.random.default_rng(c["seed"])
+    specs = []
+    for i in range(c["n_jobs"]):
+        H = max(16, log_uniform_side(rng, c["side_lo"], c["side_hi"]) // scale)
+        W = max(16, log_uniform_side(rng, c["side_lo"], c["side_hi"]) // scale)
+        cls, h = random_psf(rng)
+        K = int(rng.integers(c["K_lo"], c["K_hi"] + 1))
+        specs.append(dict(name=f"b{i}-{cls}", H=H, W=W, h=h, iters=K, seed=1000 + i,
+                          noise="poisson", peak=c["peak"]))
+    return specs
+
+
+def _make_from_spec(s):
+    return make_job(s["name"], s["H"], s["W"], s["h"], s["iters"], s["seed"],
+                    noise=s["noise"], peak=s["peak"])
+
+
+def make_jobs(specs, workers=1, pool="thread"):
+    """Images of every spec, in spec order.  workers > 1 spreads them over a pool of
+    threads, or of forked processes (pool="fork"; only before the process has touched a
+    GPU).  The result does not depend on the pool."""
+    if workers <= 1:
+        return [_make_from_spec(s) for s in specs]
+    if pool == "fork":
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as p:
+            return p.map(_make_from_spec, specs, chunksize=1)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(_make_from_spec, specs))

@@ -88,4 +88,63 @@ def test_summaries_of_a_size_sweep_run(tmp_path):
     _pmc(tmp_path / "f", "FETCH_SIZE", [(copy, 512.0), (span, 1000.0)])
     _pmc(tmp_path / "w", "WRITE_SIZE", [(copy, 1024.0), (span, 400.0)])
     text = bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), 1, "cmd", 4096)
-    assert "at 4096 x 4096: 12 B per pixel" in text and "= 192.0 MiB" in text
+    assert "at 4096 x 4096: 6 B per pixel" in text and "= 96.0 MiB" in text
+
+
+def test_pooled_traffic_over_template_instances(tmp_path):
+    """Two kernel symbols with one registry name: bytes_per_launch is their scaled total
+    over their dispatch count."""
+    a = "void rlk::span_kernel<0, 8, 16, 8, false>(rlk::LaunchArgs)"
+    b = "void rlk::span_kernel<1, 4, 8, 8, false>(rlk::LaunchArgs)"
+    copy = "__amd_rocclr_copyBuffer"
+    _pmc(tmp_path / "f", "FETCH_SIZE", [(copy, 512.0), (a, 100.0), (a, 300.0), (b, 50.0)])
+    _pmc(tmp_path / "w", "WRITE_SIZE", [(copy, 1024.0), (a, 10.0), (a, 10.0), (b, 40.0)])
+    text = bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), 1, "cmd")
+    data = json.loads(text[text.index("```json") + 7:text.rindex("```")])
+    want = ((100 + 300 + 50) * 2 + (10 + 10 + 40)) * 1024 / 3
+    assert data["bytes_per_launch"]["span_conv_ratio"] == round(want)
+
+
+class _FakeAbi:
+    RL_SCHED_RESIDENT, RL_PATH_BOX_RECT, RL_PATH_BOX_SAT = 2, 4, 5
+
+
+def test_roofline_accounting():
+    """12 B per pixel-iteration: 6 B per output of each phase launch, 12 B x K per
+    output of a resident launch; the bound is the resource with the longer minimum
+    time."""
+    import numpy as np
+    jobs = [dict(name="a", f=np.zeros((100, 50), np.float32), iters=10),
+            dict(name="b", f=np.zeros((20, 10), np.float32), iters=4),
+            dict(name="c", f=np.zeros((30, 30), np.float32), iters=7)]
+    infos = {"a": dict(schedule=1, path=3, lmax=0, n_spans=21, n_taps=317),
+             "b": dict(schedule=1, path=3, lmax=0, n_spans=21, n_taps=317),
+             "c": dict(schedule=2, path=2, lmax=0, n_spans=1, n_taps=41)}
+    work = bench.kernel_work(_FakeAbi, jobs, infos)
+    px_it = 5000 * 10 + 200 * 4
+    assert work["slide_conv_ratio"]["bytes"] == 6.0 * px_it
+    assert work["slide_corr_update"]["flops"] == (2 * 21 + 1) * px_it
+    assert work["resident_box"]["bytes"] == 12.0 * 900 * 7
+    # 10 launches of 1 us each: bytes per launch 6 B x px_it / 10
+    kernels = {"slide_conv_ratio": dict(launches=10, total_ms=0.01, avg_us=1.0),
+               "resident_box": dict(launches=1, total_ms=0.001, avg_us=1.0)}
+    rf = bench.roofline_of(kernels, work, lambda nm: None)
+    assert rf["kernel"] == "slide_conv_ratio"
+    by = 6.0 * px_it / 10
+    fl = (2 * 21 + 1) * px_it / 10
+    assert rf["bytes_per_launch"] == round(by)
+    # 43 flops per 6 B (7.2 flop/B) is below the machine balance (157.3e12 / 8e12 =
+    # 19.7 flop/B): HBM binds
+    assert rf["bound"] == "hbm"
+    assert abs(rf["achieved"] - by / 1e-6 / 1e9) < 1e-2
+    assert abs(rf["frac"] - by / 1e-6 / 1e9 / bench.PEAK_HBM_GBS) < 1e-5
+    assert abs(rf["alu_frac"] - fl / 1e-6 / 1e12 / bench.PEAK_FP32_TFLOPS) < 1e-5
+    # a dense 15 x 15 PSF (451 flops per output of a phase) is bound by the ALUs
+    infos["a"] = dict(schedule=1, path=3, lmax=16, n_spans=15, n_taps=225)
+    infos["b"] = dict(infos["a"])
+    work = bench.kernel_work(_FakeAbi, jobs, infos)
+    kernels = {"span_corr_update": dict(launches=10, total_ms=0.01, avg_us=1.0)}
+    rf = bench.roofline_of(kernels, work, lambda nm: None)
+    assert rf["bound"] == "alu" and rf["unit"] == "TFLOP/s"
+    fl = (2 * 225 + 1) * px_it / 10
+    assert abs(rf["frac"] - fl / 1e-6 / 1e12 / bench.PEAK_FP32_TFLOPS) < 1e-5

@@ -2,10 +2,12 @@
 
 Lock-step protocol: a state (u^k, r, cnt, k) is produced by the FP64 oracle, rounded to
 float32 and handed to both sides; each side performs one iteration.  Floats must agree
-within RTOL; the per-pixel counters must agree bit for bit except at pixels whose
-convergence test lies within float32 rounding of the threshold (both decisions are then
-valid; such pixels are counted and checked for validity).  The compacted active-pixel
-list must equal numpy.flatnonzero of the mask bit for bit (P11).
+within RTOL.  The convergence test is defined on the float32 values the GPU holds
+(Section 4's threshold test on u^{k+1} and u^k): the oracle's float32 decision
+(``below_many``) evaluated on the GPU's own u^{k+1} and the float32 u^k gives the expected
+counter of every active pixel, and the GPU's counters must equal it bit for bit
+everywhere, with no rounding band.  The compacted active-pixel list must equal
+numpy.flatnonzero of the mask bit for bit (P11).
 """
 import numpy as np
 import pytest
@@ -26,33 +28,13 @@ REL = dict(mode="rel", tau=1e-3, hysteresis=3, reset_period=10, compact_period=1
 PAPER = dict(mode="abs", tau=0.02 / 255 * 40, hysteresis=1, reset_period=10, compact_period=1)
 
 
-def _decision(a32, b32, mode, tau):
-    a32 = np.float32(a32)
-    b32 = np.float32(b32)
-    t = np.float32(tau) * b32 if mode == "rel" else np.float32(tau)
-    return bool(np.abs(np.float32(a32 - b32)) < t)
-
-
-def _expected_cnt(cnt0, active, a64, b32, thin, delta=4e-7):
-    """Counter after one step, and the mask of pixels whose decision is ambiguous."""
-    cnt = cnt0.copy()
-    amb = np.zeros(cnt0.shape, bool)
-    tau = np.float32(thin["tau"])
-    for idx in zip(*np.nonzero(active)):
-        a, b = a64[idx], b32[idx]
-        if not tau > 0:
-            d = [False]
-        elif b == 0 and a == 0:
-            d = [True]
-        else:
-            d = {_decision(a * (1 - delta), b, thin["mode"], tau), _decision(a, b, thin["mode"], tau),
-                 _decision(a * (1 + delta), b, thin["mode"], tau)}
-        d = list(d)
-        if len(d) > 1:
-            amb[idx] = True
-            continue
-        cnt[idx] = min(int(cnt0[idx]) + 1, 255) if d[0] else 0
-    return cnt, amb
+def expected_counters(orc, cnt0, active, gpu_u1, u0_32, thin):
+    """Counters after one step when the GPU's float32 u^{k+1} and u^k decide: active
+    pixels count up (saturating at 255) where the float32 test says "below", else reset
+    to 0; frozen pixels keep their counter."""
+    below = orc.below_many(gpu_u1, u0_32, thin["mode"], thin["tau"])
+    up = np.minimum(cnt0.astype(np.int32) + 1, 255).astype(np.uint8)
+    return np.where(active, np.where(below, up, np.uint8(0)), cnt0).astype(np.uint8)
 
 
 def _oracle_state(orc, f, h, thin, k0):
@@ -102,13 +84,14 @@ def _lockstep(orc, thin, k0, h, path="auto"):
     assert np.array_equal(gu[~active], u32[~active])
     assert np.array_equal(gr[~active], r32[~active])
     assert sched[-1] == n_act
-    want, amb = _expected_cnt(cnt, active, u, u32, thin)
-    assert np.array_equal(c[~amb], want[~amb])  # the oracle agrees with its own decision
-    mism = (gc != want) & ~amb
-    assert not mism.any(), f"{mism.sum()} counter mismatches outside the ambiguity band"
-    ok_amb = (gc[amb] == 0) | (gc[amb] == np.minimum(cnt[amb].astype(int) + 1, 255))
-    assert ok_amb.all()
-    print(f"k0={k0} active={n_act} ambiguous={int(amb.sum())}")
+    want = expected_counters(orc, cnt, active, gu, u32, thin)
+    mism = gc != want
+    assert not mism.any(), f"{int(mism.sum())} counters differ from the float32 decision"
+    # the oracle's own step decides on its FP64 u^{k+1} rounded to float32; it may differ
+    # from the GPU's decision only where the two float32 values differ
+    differ = (c != gc) & active
+    assert np.all(gu[differ].astype(np.float32) != u.astype(np.float32)[differ])
+    print(f"k0={k0} active={n_act} oracle-vs-GPU decisions differing: {int(differ.sum())}")
 
 
 @pytest.mark.parametrize("mode", ["abs", "rel"])
@@ -184,10 +167,14 @@ def test_free_running_small_config3_analogue(orc):
     print(f"free-running: u max err {err:.3g}, pixels above {RTOL}: {outside:.3g}, mask "
           f"disagreement {mask_dis:.3g}, schedule deviation {sched_dev:.3g}, omitted {omitted:.4f}")
     assert stats.skipped_px_iters == K * f.size - int(sched.sum())
-    # a pixel that freezes one iteration earlier on one side keeps a u that differs by
-    # about tau per missed update; only those pixels and their neighbourhoods may leave
-    # the float tolerance
+    # A pixel that freezes on one side and not on the other misses at most R - 1 updates
+    # before the next full step recomputes it, each a relative change below tau (the test
+    # that froze it), so one such episode moves u by less than (R - 1) tau.  The bound
+    # allows two episodes per pixel in K = 60 iterations (a first freeze and one re-freeze
+    # after a full step) plus a margin of 2 tau for what the deviation feeds into its
+    # neighbours through the PSF: 2 (R - 1) tau + 2 tau = 2e-3 at tau = 1e-4, R = 10.
+    bound = 2 * (thin["reset_period"] - 1) * thin["tau"] + 2 * thin["tau"]
     assert mask_dis < 1e-3
     assert sched_dev < 1e-3
     assert outside < 1e-2
-    assert err < 1e-2
+    assert err < bound, (err, bound)
