@@ -163,16 +163,25 @@ typedef struct rl_job rl_job;
 /* Status name, e.g. "RL_E_INVAL".  Never NULL. */
 const char *rl_status_str(rl_status s);
 
+/* Text of the reason the last failing call on this thread gave (empty if it gave none),
+ * e.g. why a path does not apply to a PSF or why a workspace is too small.  Never NULL;
+ * valid until the next library call on this thread. */
+const char *rl_last_error(void);
+
 /*
- * Exact number of device bytes rl_init needs for these parameters (f, u and r planes,
- * the compiled PSF, thinning state, reduction scratch).  Pure host computation.
- * Returns RL_E_INVAL for invalid sizes or PSF (PSF values are read from p->psf).
+ * Exact number of device bytes rl_init needs for these parameters: the planes of eq. 3
+ * (f, u^k and the ratio r = f / (u^k * h), Section 2), the compiled PSF (Section 3),
+ * the thinning state of Section 4 (counters, active lists), reduction scratch.  Pure host
+ * computation.  Returns RL_E_INVAL for invalid sizes or PSF (PSF values are read from
+ * p->psf).
  */
 rl_status rl_workspace_bytes(const rl_params *p, size_t *bytes);
 
 /*
- * Validate p, compile the PSF (host), and enqueue on p->stream: the upload of the compiled
- * PSF, the copy of f (and u0) into the workspace, and zeroing of the thinning state.
+ * Set up one problem f ~ u*h (Section 1, eq. 2) for RL iteration from u^0 = f (Section 2,
+ * eq. 3): validate p, compile the PSF (host, Section 3), and enqueue on p->stream: the
+ * upload of the compiled PSF, the copy of f (and u0) into the workspace, and zeroing of
+ * the thinning state (Section 4).
  * ws: caller-owned device buffer of ws_bytes >= rl_workspace_bytes(p), 256-byte aligned;
  * it must stay alive and untouched until rl_destroy.  f's sign and finiteness are checked
  * on the GPU; the outcome is reported by rl_result (RL_E_INVAL) and in rl_stats.f_invalid.
@@ -189,10 +198,13 @@ rl_status rl_init(const rl_params *p, void *ws, size_t ws_bytes, rl_job **out);
 rl_status rl_iterate(rl_job *job, int32_t n_iter);
 
 /*
- * Enqueue a device-to-device copy of u^k into u_out (height*width floats, may be NULL to
- * skip).  If st is non-NULL, also reduce the statistics on the GPU, synchronise the job's
- * stream and fill *st.  Returns RL_E_INVAL if f was found invalid (only known once the
- * stream has been synchronised, i.e. when st != NULL).
+ * The result of the iteration (Section 2, eq. 3; Section 4, eq. 4-5 when thinned): enqueue
+ * a device-to-device copy of u^k into u_out (height*width floats, may be NULL to skip).
+ * If st is non-NULL, also reduce the statistics on the GPU, synchronise the job's stream
+ * and fill *st.  Returns RL_E_INVAL if f was found invalid (only known once the stream has
+ * been synchronised, i.e. when st != NULL).  A job that has run the persistent schedule
+ * also synchronises the stream without st, to read its launches' abort flag: RL_E_DEVICE
+ * if a launch gave up waiting (u^k is then incomplete).
  */
 rl_status rl_result(rl_job *job, float *u_out, rl_stats *st);
 
@@ -220,7 +232,9 @@ rl_status rl_iterate_batch(rl_job *const *jobs, const int32_t *n_iter, int32_t n
                            void *bws, size_t bws_bytes, void *stream);
 
 /*
- * Lock-step / checkpoint hooks (enqueued on the job's stream, asynchronous):
+ * Lock-step / checkpoint hooks (enqueued on the job's stream, asynchronous; rl_get_state
+ * of a job that has run the persistent schedule synchronises to check the abort flag, as
+ * rl_result does):
  *   rl_get_state copies u^k, the persistent ratio r (thinned mode keeps stale values of
  *   inactive pixels) and the per-pixel convergence counters out of the workspace, and
  *   writes k to *k_out (host).  Any of u, r, cnt may be NULL.
@@ -255,6 +269,13 @@ rl_status rl_thin_schedule(rl_job *job, int64_t *out, int32_t cap, int32_t *n);
  */
 rl_status rl_psf_runs(const float *psf, int32_t psf_h, int32_t psf_w, int32_t *runs,
                       float *w, int32_t cap, int32_t *n_runs, int32_t *cls);
+
+/* Test hook for the failure path of the persistent schedule: the number of polls a
+ * dependency wait of later persistent launches makes before the launch gives up (sets its
+ * abort flag; every workgroup then leaves, so the kernel ends).  Default 1 << 20; a
+ * negative value gives up at the first wait of every launch.  *previous (may be NULL)
+ * receives the old value.  Process-wide. */
+rl_status rl_debug_spin_limit(int32_t polls, int32_t *previous);
 
 /* Kernel timing for measurement: while enabled, every kernel launch of every job is
  * bracketed by HIP events on the stream it is launched on.  rl_timing_read synchronises

@@ -31,7 +31,7 @@ EXPORTS = ["rl_status_str", "rl_workspace_bytes", "rl_init", "rl_iterate", "rl_r
            "rl_set_state", "rl_active_list", "rl_thin_schedule", "rl_psf_runs",
            "rl_timing_enable", "rl_timing_read", "rl_timing_reset", "rl_autotune_workspace_bytes",
            "rl_autotune", "rl_tune_lookup", "rl_tune_cache_save", "rl_tune_cache_load",
-           "rl_tune_cache_clear", "rl_job_describe"]
+           "rl_tune_cache_clear", "rl_job_describe", "rl_debug_spin_limit", "rl_last_error"]
 
 
 class rl_thin(ctypes.Structure):
@@ -73,7 +73,9 @@ class rl_job_info(ctypes.Structure):
 class RLError(RuntimeError):
     def __init__(self, fn, status):
         self.status = status
-        super().__init__(f"{fn} failed: {status_str(status)} ({status})")
+        why = last_error()
+        super().__init__(f"{fn} failed: {status_str(status)} ({status})"
+                         + (f": {why}" if why else ""))
 
 
 _lib = None
@@ -114,6 +116,8 @@ def lib():
             "rl_tune_cache_load": (i32, [ctypes.c_char_p]),
             "rl_tune_cache_clear": (i32, []),
             "rl_job_describe": (i32, [vp, P(rl_job_info)]),
+            "rl_debug_spin_limit": (i32, [i32, P(i32)]),
+            "rl_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -125,6 +129,10 @@ def lib():
 
 def status_str(s):
     return lib().rl_status_str(int(s)).decode()
+
+
+def last_error():
+    return (lib().rl_last_error() or b"").decode()
 
 
 def check(fn, status):
@@ -157,6 +165,13 @@ def rl_result(job, u_out_ptr=None, want_stats=False):
                         ctypes.byref(st) if want_stats else None)
     check("rl_result", s)
     return st if want_stats else None
+
+
+def rl_debug_spin_limit(polls):
+    """Set the persistent schedule's wait limit (test hook); returns the previous one."""
+    prev = ctypes.c_int32(0)
+    check("rl_debug_spin_limit", lib().rl_debug_spin_limit(int(polls), ctypes.byref(prev)))
+    return prev.value
 
 
 def rl_destroy(job):

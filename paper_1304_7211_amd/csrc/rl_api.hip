@@ -5,6 +5,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <fstream>
 #include <sstream>
@@ -657,6 +658,10 @@ int persist_capacity(PersistFn fn, size_t lds) {
 }
 
 constexpr int kSpinLimit = 1 << 20;  // polls (about a second) before a persistent launch gives up
+std::atomic<int> g_spin_limit{kSpinLimit};  // rl_debug_spin_limit changes it for tests
+
+// After a persistent launch: read its sticky abort flag (synchronises the job's stream).
+rl_status check_persist_abort(rl_job* j, hipStream_t s);
 
 PhaseFn phase_fn(const Config& c, bool phase_b) {
     if (c.kind == KIND_RECT) {
@@ -946,7 +951,7 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
         P.n_jobs = 1;
         P.total_tiles = ntiles;
         P.max_steps = 2 * n;
-        P.spin_limit = kSpinLimit;
+        P.spin_limit = g_spin_limit.load();
         P.ticket = pctl;
         P.abort = pctl + 1;
         P.one.a = phase_args(j, false, j->k);
@@ -1083,6 +1088,19 @@ std::vector<DevSpan> to_dev(const rl::OpTable& t) {
     return v;
 }
 
+rl_status check_persist_abort(rl_job* j, hipStream_t s) {
+    int32_t flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, j->at<int32_t>(j->L.pctl) + 1, sizeof flag,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (rl_status st = dev_err(e, "read abort flag")) return st;
+    if (flag) {
+        g_last_error = "a persistent launch exceeded its wait limit; the result is incomplete";
+        return RL_E_DEVICE;
+    }
+    return RL_OK;
+}
+
 }  // namespace
 
 namespace {  // autotuner helpers
@@ -1141,6 +1159,8 @@ const char* rl_status_str(rl_status s) {
     return "RL_E_UNKNOWN";
 }
 
+const char* rl_last_error(void) { return g_last_error.c_str(); }
+
 rl_status rl_workspace_bytes(const rl_params* p, size_t* bytes) {
     std::string why;
     if (!bytes) return RL_E_INVAL;
@@ -1155,8 +1175,16 @@ rl_status rl_workspace_bytes(const rl_params* p, size_t* bytes) {
     return RL_OK;
 }
 
-rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
-    std::string why;
+}  // extern "C"
+
+namespace {
+
+// rl_init's body.  no_alloc: no pinned host word and no event for the asynchronous
+// active-tile count (the tile list is then always used), so that set-up performs no
+// allocation at all.
+rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, bool no_alloc) {
+    std::string& why = g_last_error;  // reasons of rejections are kept for rl_last_error
+    why.clear();
     if (!out || !ws) return RL_E_INVAL;
     *out = nullptr;
     rl_status st = validate_params(p, &why);
@@ -1249,7 +1277,7 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     }
     if ((st = dev_err(launch("check_f", rlk::check_f_kernel, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s,
                              (const float*)j->at<float>(j->L.f), N, reinterpret_cast<int32_t*>(j->at<int64_t>(j->L.ctr) + C_F_INVALID)), "check f"))) { delete j; return st; }
-    if (p->thin.mode != RL_THIN_OFF) {
+    if (p->thin.mode != RL_THIN_OFF && !no_alloc) {
         // pinned word and event for the asynchronous active-tile count (optional: without
         // them the tile list is always used)
         if (hipHostMalloc((void**)&j->h_tcount, sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
@@ -1262,6 +1290,14 @@ rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
     }
     *out = j;
     return RL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rl_status rl_init(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out) {
+    return init_job(p, ws, ws_bytes, out, false);
 }
 
 rl_status rl_iterate(rl_job* j, int32_t n_iter) {
@@ -1279,7 +1315,7 @@ rl_status rl_result(rl_job* j, float* u_out, rl_stats* st) {
     if (u_out) {
         if ((rs = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(grid_for(j->N)), dim3(256), 0, s, u_out, (const float*)j->cur_u(), j->N), "copy u"))) return rs;
     }
-    if (!st) return RL_OK;
+    if (!st) return j->persist_used ? check_persist_abort(j, s) : RL_OK;
     int64_t* ctr = j->at<int64_t>(j->L.ctr);
     const bool thin = j->p.thin.mode != RL_THIN_OFF;
     if (thin && (rs = finalize_thin(j, s))) return rs;
@@ -1517,7 +1553,7 @@ rl_status rl_get_state(rl_job* j, float* u, float* r, uint8_t* cnt, int64_t* k_o
         if ((st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, cnt, (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N), "get cnt"))) return st;
     }
     if (k_out) *k_out = j->k;
-    return RL_OK;
+    return j->persist_used ? check_persist_abort(j, s) : RL_OK;
 }
 
 rl_status rl_set_state(rl_job* j, const float* u, const float* r, const uint8_t* cnt, int64_t k) {
@@ -1596,6 +1632,12 @@ rl_status rl_psf_runs(const float* psf, int32_t psf_h, int32_t psf_w, int32_t* r
         }
         if (w) w[i] = c.runs[i].w;
     }
+    return RL_OK;
+}
+
+rl_status rl_debug_spin_limit(int32_t polls, int32_t* previous) {
+    const int old = g_spin_limit.exchange(polls);
+    if (previous) *previous = old;
     return RL_OK;
 }
 

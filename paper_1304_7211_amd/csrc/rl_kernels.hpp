@@ -1291,7 +1291,8 @@ __device__ __forceinline__ bool wait_deps(const PersistJob& J, int t, int s, int
     const int b_lo = max(0, tb - J.reach_b), b_hi = min(tb_n - 1, tb + J.reach_b);
     const int na = a_hi - a_lo + 1, nd = na * (b_hi - b_lo + 1);
     for (int spins = 0;; ++spins) {
-        bool ready = true;
+        // spin_limit < 0 (a host-set test condition) gives up at the first poll
+        bool ready = spin_limit >= 0;
         for (int d = lane; d < nd; d += 64) {
             const int y = b_lo + d / na, x = a_lo + d % na;
             if (poll_done(J.done + y * ta_n + x) < s) ready = false;

@@ -262,3 +262,13 @@ def test_tune_cache_roundtrip(A, tmp_path):
         A.rl_tune_cache_load(tmp_path / "missing.txt")
     A.rl_tune_cache_clear()
     assert A.rl_tune_lookup(p) is None
+
+
+def test_last_error_names_the_reason(A):
+    L = A.lib()
+    p, keep = _params(A, psf=synth.disc(3), path=A.RL_PATH_BOX_AXIS)
+    job = ctypes.c_void_p(0)
+    ws = ctypes.c_void_p(256)  # never dereferenced: the PSF check fails first
+    p.f = 256
+    assert L.rl_init(ctypes.byref(p), ws, 1 << 20, ctypes.byref(job)) == A.RL_E_INVAL
+    assert "BOX_AXIS" in A.last_error()

@@ -90,3 +90,36 @@ def test_persistent_rejects_thinning():
     f = _obs(100, 90, h, 3)
     with pytest.raises(RLError):
         Job(to_dev(f), h, schedule="persistent", thin=dict(mode="rel", tau=1e-3))
+
+
+def test_wait_limit_failure_surfaces():
+    """Failure path, forced from the host: with a negative wait limit every dependency
+    wait of a persistent launch gives up at once (the kernel's own bounded wait: the launch
+    raises its abort flag and every workgroup leaves, so the kernel ends normally).  The
+    incomplete result must be reported by rl_result (with and without statistics) and by
+    rl_get_state, i.e. by Job.result(), Job.stats() and Job.get_state()."""
+    from paper_1304_7211_amd import _abi as A
+    h = synth.disc(6)
+    f = _obs(300, 280, h, 95)
+    prev = A.rl_debug_spin_limit(-1)
+    try:
+        job = Job(to_dev(f), h, path="runs", schedule="persistent")
+        job.iterate(4)
+        with pytest.raises(RLError) as e:
+            job.result()
+        assert e.value.status == A.RL_E_DEVICE and "wait limit" in str(e.value)
+        with pytest.raises(RLError):
+            job.stats()
+        with pytest.raises(RLError):
+            job.get_state()
+        job.close()
+    finally:
+        A.rl_debug_spin_limit(prev)
+    torch.cuda.synchronize()
+    # the limit is restored: a new job completes and matches two-pass bit for bit
+    ok = Job(to_dev(f), h, path="runs", schedule="persistent")
+    ok.iterate(4)
+    u = ok.result().cpu().numpy()
+    ok.close()
+    ref, _ = run_gpu(f, h, 4, path="runs", schedule="two_pass")
+    assert np.array_equal(u.astype(np.float64), ref)
