@@ -248,6 +248,8 @@ def main():
                     help="also time the other mode (reported as 'other_mode')")
     ap.add_argument("--report", type=int, choices=[1, 3, 4, 5, 6, 7], default=None)
     ap.add_argument("--requests", type=int, default=1000, help="--report 5: requests")
+    ap.add_argument("--pool-size", type=int, default=256,
+                    help="--report 5: distinct requests the arrivals are drawn from")
     ap.add_argument("--sides", default="512,1024,2048,4096",
                     help="--report 7: image sides, comma-separated")
     ap.add_argument("--summary-side", type=int, default=0,
@@ -287,6 +289,14 @@ def main():
 
     import synth
     jobs = None
+    if args.report == 5:
+        # the request pool first, in forked workers, before anything touches the GPU
+        from synth.configs import make_jobs, serving_specs
+        t0 = time.perf_counter()
+        workers = max(1, min(16, os.cpu_count() or 1))
+        args.pool = make_jobs(serving_specs(args.pool_size), workers=workers, pool="fork")
+        log(f"report 5: pool of {len(args.pool)} distinct requests generated in "
+            f"{time.perf_counter() - t0:.1f}s")
     if args.report is None and args.workload == "batched":
         # images first, in forked workers, before anything touches the GPU
         t0 = time.perf_counter()
@@ -647,33 +657,27 @@ def report_serving(args, dev):
     import torch
 
     import synth
-    from synth.configs import log_uniform_side, random_psf
     from paper_1304_7211_amd.serve import (Request, Server, latency_report, run_stream,
                                            serve_plain)
     c = synth.CONFIGS[5]
-    rng = np.random.default_rng(c["seed"])
+    rng = np.random.default_rng(c["seed"] + 1)
     thin = dict(synth.CONFIGS[3]["thin"])
-    pool = []
-    t0 = time.perf_counter()
-    for i in range(24):
-        H = log_uniform_side(rng, c["side_lo"], c["side_hi"])
-        W = log_uniform_side(rng, c["side_lo"], c["side_hi"])
-        _, h = random_psf(rng)
-        K = int(rng.integers(c["K_lo"], c["K_hi"] + 1))
-        f = synth.observe(synth.latent_image(H, W, 500 + i), h, "poisson", 500 + i)
-        pool.append((f, h, K))
-    log(f"report 5: pool of {len(pool)} requests generated in {time.perf_counter() - t0:.1f}s")
+    pool = [(j["f"], j["psf"], j["iters"]) for j in args.pool]
     pool_dev = [(torch.from_numpy(f).to(dev), h, K) for f, h, K in pool]
     budget = int(0.5 * torch.cuda.mem_get_info(dev)[0])
+    # every arrival draws its request from the pool (uniformly, seeded); the first
+    # len(pool) arrivals cover the pool in a shuffled order
+    order = np.concatenate([rng.permutation(len(pool)),
+                            rng.integers(0, len(pool), size=max(0, args.requests - len(pool)))])
 
     def make(n, arrivals):
-        return [Request(i, pool_dev[i % len(pool)][0], pool_dev[i % len(pool)][1],
-                        pool_dev[i % len(pool)][2], thin=thin, arrival=float(a))
+        return [Request(i, pool_dev[order[i % len(order)]][0], pool_dev[order[i % len(order)]][1],
+                        pool_dev[order[i % len(order)]][2], thin=thin, arrival=float(a))
                 for i, a in enumerate(arrivals)]
 
-    # capacity: everything submitted at once
+    # capacity: the whole pool submitted at once
     warm = Server(budget, max_slots=64, chunk=10)
-    run_stream(make(len(pool), [0.0] * len(pool)), warm)
+    run_stream(make(min(32, len(pool)), [0.0] * min(32, len(pool))), warm)
     srv = Server(budget, max_slots=64, chunk=10)
     reqs = make(len(pool), [0.0] * len(pool))
     dt = run_stream(reqs, srv)
@@ -691,7 +695,8 @@ def report_serving(args, dev):
     dt_p = serve_plain(base)
     rep_p = latency_report(base)
     same = all(torch.equal(a.result, b.result) for a, b in zip(reqs, base))
-    px_it = sum(pool[i % len(pool)][0].size * pool[i % len(pool)][2] for i in range(n))
+    px_it = sum(pool[order[i % len(order)]][0].size * pool[order[i % len(order)]][2]
+                for i in range(n))
     log(f"report 5: continuous {rep_c}, plain {rep_p}, identical={same}")
     del base
     # load sweep of the continuous-batching server (same request mix, other arrival rates)
@@ -707,8 +712,9 @@ def report_serving(args, dev):
         del rs
     return {
         "report": "serving, config 5",
-        "workload": f"{n} requests from a pool of {len(pool)} (sides 128..4096, mixed PSFs, "
-                    "50..500 iterations, thinning rel 1e-4 H5 R10 C10), Poisson arrivals",
+        "workload": f"{n} requests, each drawn from {len(pool)} distinct seeded requests "
+                    "(sides 128..4096, mixed PSFs, 50..500 iterations, thinning rel 1e-4 H5 "
+                    "R10 C10), Poisson arrivals",
         "qps": qps,
         "batched_capacity_req_per_s": capacity,
         "continuous": dict(latency=rep_c, wall_s=dt_c, px_it_per_s=px_it / dt_c,

@@ -13,6 +13,12 @@ input and output images on the device.  A request larger than the whole budget i
 rejected; otherwise it waits in arrival order (no overtaking, so a large request is not
 starved by small ones).
 
+A request can be cancelled (``Server.cancel``) or given a deadline (``Request.deadline``,
+seconds after its arrival): a waiting request is dropped, a running one leaves the batch
+at the next tick; either way its slot and budget are released at once, so the next
+waiting request is admitted in the same tick.  A request whose result copy has already
+been enqueued completes normally.
+
 ``serve_plain`` is the reference form: one request at a time, in arrival order, each
 solved alone with rl_iterate.
 
@@ -30,7 +36,8 @@ from .job import BatchRunner, Job
 
 
 class Request:
-    def __init__(self, rid, f, psf, iters, thin=None, arrival=0.0, path="auto"):
+    def __init__(self, rid, f, psf, iters, thin=None, arrival=0.0, path="auto",
+                 deadline=None):
         self.rid = rid
         self.f = f                # numpy float32 (H, W) on the host, or a CUDA tensor
         self.psf = np.ascontiguousarray(psf, dtype=np.float32)
@@ -38,11 +45,13 @@ class Request:
         self.thin = thin
         self.arrival = float(arrival)
         self.path = path
+        self.deadline = None if deadline is None else float(deadline)  # s after arrival
         # filled by the server
         self.admitted = None
         self.completed = None
         self.result = None
         self.footprint = None
+        self.status = "new"       # pending, running, done, cancelled, timeout, rejected
 
     @property
     def shape(self):
@@ -115,6 +124,7 @@ class Server:
         self.in_flight = []       # list of (event, [(req, job, f_dev, out)])
         self.done = []
         self.rejected = []
+        self.cancelled = []       # cancelled and timed-out requests
         self.runner = BatchRunner(max_slots, self.device)
         self.ticks = 0
 
@@ -123,10 +133,47 @@ class Server:
         req.footprint = request_footprint(req, self.device)
         if not self.ctl.fits_ever(req.footprint):
             req.completed = float("nan")
+            req.status = "rejected"
             self.rejected.append(req)
             return False
+        req.status = "pending"
         self.pending.append(req)
         return True
+
+    def cancel(self, rid, status="cancelled", now=None):
+        """Drop request ``rid`` if it is still waiting or running: a running job leaves the
+        batch (its device state is freed on the server stream, after the work already
+        enqueued for it) and its slot and budget are released.  Returns False if the
+        request is unknown here or its result is already on its way."""
+        now = time.perf_counter() if now is None else now
+        for req in self.pending:
+            if req.rid == rid:
+                self.pending.remove(req)
+                self._end(req, status, now)
+                return True
+        for a in self.active:
+            if a[0].rid == rid:
+                self.active.remove(a)
+                req, job = a[0], a[1]
+                job.close()
+                self.ctl.release(req.footprint)
+                self._end(req, status, now)
+                return True
+        return False
+
+    def _end(self, req, status, now):
+        req.status = status
+        req.completed = now
+        req.result = None
+        self.cancelled.append(req)
+
+    def _expire(self, now):
+        late = [r.rid for r in self.pending if r.deadline is not None
+                and now > r.arrival + r.deadline]
+        late += [a[0].rid for a in self.active if a[0].deadline is not None
+                 and now > a[0].arrival + a[0].deadline]
+        for rid in late:
+            self.cancel(rid, status="timeout", now=now)
 
     def _admit(self, now):
         while self.pending:
@@ -139,6 +186,7 @@ class Server:
                     torch.from_numpy(np.ascontiguousarray(req.f)).to(self.device, non_blocking=False)
                 job = Job(f_dev, req.psf, thin=req.thin, path=req.path, stream=self.stream)
             req.admitted = now
+            req.status = "running"
             self.active.append([req, job, f_dev, req.iters])
 
     # -- one tick ------------------------------------------------------------------------
@@ -152,6 +200,7 @@ class Server:
                 for req, job, f_dev, out in items:
                     req.completed = t
                     req.result = out
+                    req.status = "done"
                     job.close()
                     self.ctl.release(req.footprint)
                     self.done.append(req)
@@ -164,6 +213,7 @@ class Server:
         results of jobs that finished, and retire jobs whose results are complete."""
         now = time.perf_counter() if now is None else now
         self._retire_finished()
+        self._expire(now)
         self._admit(now)
         if not self.active:
             return False
@@ -244,12 +294,14 @@ def serve_plain(requests, device=None, stream=None):
         stream.synchronize()
         r.completed = time.perf_counter()
         r.result = out
+        r.status = "done"
         job.close()
     return time.perf_counter() - t0
 
 
 def latency_report(requests):
-    lat = np.array([r.completed - r.arrival for r in requests if r.completed == r.completed])
+    lat = np.array([r.completed - r.arrival for r in requests
+                    if r.completed == r.completed and r.status == "done"])
     if lat.size == 0:
         return dict(n=0)
     return dict(n=int(lat.size), p50_ms=float(1e3 * np.percentile(lat, 50)),

@@ -93,6 +93,23 @@ def batched_specs(scale=1):
     return specs
 
 
+def serving_specs(n):
+    """Parameters of n distinct serving requests (sides log-uniform in 128..4096, PSFs as
+    in the batched workload, 50..500 iterations), drawn in order from one seeded stream;
+    each image comes from its own seed."""
+    c = CONFIGS[5]
+    rng = np.random.default_rng(c["seed"])
+    specs = []
+    for i in range(int(n)):
+        H = log_uniform_side(rng, c["side_lo"], c["side_hi"])
+        W = log_uniform_side(rng, c["side_lo"], c["side_hi"])
+        cls, h = random_psf(rng)
+        K = int(rng.integers(c["K_lo"], c["K_hi"] + 1))
+        specs.append(dict(name=f"s{i}-{cls}", H=H, W=W, h=h, iters=K, seed=500 + i,
+                          noise=c["noise"], peak=c["peak"]))
+    return specs
+
+
 def _make_from_spec(s):
     return make_job(s["name"], s["H"], s["W"], s["h"], s["iters"], s["seed"],
                     noise=s["noise"], peak=s["peak"])

@@ -96,3 +96,64 @@ def test_stream_and_plain_reference():
     for a, b in zip(sorted(reqs, key=lambda r: r.rid), sorted(base, key=lambda r: r.rid)):
         assert np.array_equal(a.result.cpu().numpy(), b.result.cpu().numpy())
     print("continuous", rep, "plain", rep0)
+
+
+def test_cancel_frees_the_slot_and_admits_the_next():
+    """Cancelling a running request mid-stream: it leaves the batch, its slot and budget
+    are released in the same call, the next waiting request is admitted at the next tick,
+    and every other result is still bit-identical to the request solved alone."""
+    reqs = _requests(n=6, seed=11)
+    for r in reqs:
+        r.iters = max(r.iters, 30)
+    alone = {r.rid: _alone(r) for r in reqs}
+    srv = Server(budget_bytes=1 << 40, max_slots=2, chunk=5)
+    for r in reqs:
+        assert srv.submit(r)
+    srv.tick()
+    running = [a[0].rid for a in srv.active]
+    assert len(running) == 2 and srv.ctl.slots == 2 and len(srv.pending) == 4
+    victim = running[0]
+    assert srv.cancel(victim)
+    assert srv.ctl.slots == 1 and srv.ctl.used == reqs[running[1]].footprint
+    nxt = srv.pending[0].rid
+    srv.tick()
+    assert nxt in [a[0].rid for a in srv.active]
+    assert not srv.cancel(victim)  # already gone
+    srv.drain()
+    torch.cuda.synchronize()
+    assert reqs[victim].status == "cancelled" and reqs[victim].result is None
+    for r in reqs:
+        if r.rid != victim:
+            assert r.status == "done"
+            assert np.array_equal(r.result.cpu().numpy(), alone[r.rid]), r.rid
+    assert srv.ctl.slots == 0 and srv.ctl.used == 0
+
+
+def test_deadline_times_out_waiting_and_running_requests():
+    """A request past its deadline is dropped whether it waits or runs; the others finish
+    unchanged."""
+    reqs = _requests(n=5, seed=12)
+    for r in reqs:
+        r.iters = max(r.iters, 30)
+    alone = {r.rid: _alone(r) for r in reqs}
+    srv = Server(budget_bytes=1 << 40, max_slots=1, chunk=5)
+    t0 = 1000.0
+    for r in reqs:
+        r.arrival = t0
+    reqs[0].deadline = 0.5   # runs first, times out while running
+    reqs[3].deadline = 0.5   # still waiting when it expires
+    for r in reqs:
+        assert srv.submit(r)
+    srv.tick(now=t0)
+    assert [a[0].rid for a in srv.active] == [0]
+    srv.tick(now=t0 + 1.0)  # both expire; request 1 takes the freed slot
+    assert reqs[0].status == "timeout" and reqs[3].status == "timeout"
+    assert [a[0].rid for a in srv.active] == [1]
+    srv.drain()
+    torch.cuda.synchronize()
+    for r in reqs:
+        if r.rid not in (0, 3):
+            assert r.status == "done"
+            assert np.array_equal(r.result.cpu().numpy(), alone[r.rid])
+    rep = latency_report(reqs)
+    assert rep["n"] == 3
