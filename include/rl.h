@@ -213,6 +213,26 @@ rl_status rl_result(rl_job *job, float *u_out, rl_stats *st);
 rl_status rl_destroy(rl_job *job);
 
 /*
+ * Allocation-free solve, for callers that cannot allocate device memory: tight serving
+ * loops and harnesses that forbid hipMalloc.  One call does what rl_init, rl_iterate(n_iter),
+ * rl_result(u_out, st) and rl_destroy do for p, on p->stream, except that the job's
+ * workspace is a library-owned static device array of RL_STATIC_SCRATCH_BYTES on the
+ * current HIP device instead of a caller's buffer.  It calls no hipMalloc, hipFree or
+ * hipHostMalloc and creates no stream, event or graph (host-side bookkeeping uses ordinary
+ * heap memory; keep kernel timing off, which creates events).  p->f, p->u0 and u_out
+ * (may be NULL) are caller-owned device buffers as for rl_init / rl_result; st may be NULL.
+ * Synchronises p->stream before returning.  Each device holds one array for the life of
+ * the process; calls on one device share it and are serialised by the library (a call
+ * holds the device's lock until its GPU work has finished); the array keeps the last
+ * call's contents and each call clears what it needs zeroed.
+ * Errors: RL_E_NOMEM if rl_workspace_bytes(p) > RL_STATIC_SCRATCH_BYTES (nothing is
+ * enqueued); RL_E_UNSUPPORTED if p->tuning.graph_iters != 0; otherwise as rl_init,
+ * rl_iterate and rl_result (RL_E_INVAL also for n_iter < 0 or an invalid f).
+ */
+#define RL_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+rl_status rl_solve_static(const rl_params *p, int32_t n_iter, float *u_out, rl_stats *st);
+
+/*
  * Batched iteration of uneven jobs (different sizes, PSFs, iteration counts, thinning).
  * Enqueues n_iter[j] >= 0 further iterations of every job j on `stream` (hipStream_t;
  * the caller orders it against the jobs' own streams).  Jobs on the tiled two-pass

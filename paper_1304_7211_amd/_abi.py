@@ -31,7 +31,9 @@ EXPORTS = ["rl_status_str", "rl_workspace_bytes", "rl_init", "rl_iterate", "rl_r
            "rl_set_state", "rl_active_list", "rl_thin_schedule", "rl_psf_runs",
            "rl_timing_enable", "rl_timing_read", "rl_timing_reset", "rl_autotune_workspace_bytes",
            "rl_autotune", "rl_tune_lookup", "rl_tune_cache_save", "rl_tune_cache_load",
-           "rl_tune_cache_clear", "rl_job_describe", "rl_debug_spin_limit", "rl_last_error"]
+           "rl_tune_cache_clear", "rl_job_describe", "rl_debug_spin_limit", "rl_solve_static", "rl_last_error"]
+
+RL_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class rl_thin(ctypes.Structure):
@@ -118,6 +120,7 @@ def lib():
             "rl_job_describe": (i32, [vp, P(rl_job_info)]),
             "rl_debug_spin_limit": (i32, [i32, P(i32)]),
             "rl_last_error": (ctypes.c_char_p, []),
+            "rl_solve_static": (i32, [P(rl_params), i32, vp, P(rl_stats)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -164,6 +167,14 @@ def rl_result(job, u_out_ptr=None, want_stats=False):
     s = lib().rl_result(ctypes.c_void_p(job), ctypes.c_void_p(u_out_ptr or 0),
                         ctypes.byref(st) if want_stats else None)
     check("rl_result", s)
+    return st if want_stats else None
+
+
+def rl_solve_static(params, n_iter, u_out_ptr=None, want_stats=False):
+    st = rl_stats()
+    check("rl_solve_static", lib().rl_solve_static(
+        ctypes.byref(params), int(n_iter), ctypes.c_void_p(u_out_ptr or 0),
+        ctypes.byref(st) if want_stats else None))
     return st if want_stats else None
 
 

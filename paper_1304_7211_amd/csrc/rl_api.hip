@@ -1181,7 +1181,7 @@ namespace {
 
 // rl_init's body.  no_alloc: no pinned host word and no event for the asynchronous
 // active-tile count (the tile list is then always used), so that set-up performs no
-// allocation at all.
+// allocation at all (rl_solve_static).
 rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, bool no_alloc) {
     std::string& why = g_last_error;  // reasons of rejections are kept for rl_last_error
     why.clear();
@@ -1371,6 +1371,65 @@ rl_status rl_destroy(rl_job* j) {
     if (j->h_tcount) (void)hipHostFree(j->h_tcount);
     delete j;
     return RL_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free solve: the job workspace in a static device array ------------------
+// One array per device (each device's code object holds its own copy for the life of the
+// process).  Host code never passes the array's name to a kernel: `scratch` is a host-side
+// stand-in there; the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[RL_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];  // held by rl_solve_static for its whole call
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+
+}  // namespace
+
+extern "C" {
+
+rl_status rl_solve_static(const rl_params* p, int32_t n_iter, float* u_out, rl_stats* st) {
+    if (!p || n_iter < 0) return RL_E_INVAL;
+    if (p->tuning.graph_iters != 0) {
+        g_last_error = "rl_solve_static launches kernels directly (tuning.graph_iters must be 0)";
+        return RL_E_UNSUPPORTED;
+    }
+    size_t need = 0;
+    rl_status s = rl_workspace_bytes(p, &need);
+    if (s) return s;
+    if (need > (size_t)RL_STATIC_SCRATCH_BYTES) {
+        g_last_error = "rl_solve_static: the job needs " + std::to_string(need) +
+                       " workspace bytes, more than the static array's " +
+                       std::to_string((size_t)RL_STATIC_SCRATCH_BYTES);
+        return RL_E_NOMEM;
+    }
+    int dev = 0;
+    if ((s = dev_err(hipGetDevice(&dev), "hipGetDevice"))) return s;
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_last_error = "rl_solve_static: device index out of range";
+        return RL_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if ((s = dev_err(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)),
+                         "hipGetSymbolAddress(scratch)")))
+            return s;
+        g_scratch_ptr[dev] = ptr;
+    }
+    rl_job* j = nullptr;
+    if ((s = init_job(p, g_scratch_ptr[dev], (size_t)RL_STATIC_SCRATCH_BYTES, &j, true))) return s;
+    s = rl_iterate(j, n_iter);
+    rl_stats local;
+    if (!s) s = rl_result(j, u_out, st ? st : &local);  // synchronises the stream
+    // every enqueued copy and kernel must have finished before the host handle (the
+    // source of the table uploads) goes and before the next call reuses the array
+    const rl_status se = dev_err(hipStreamSynchronize(j->stream), "synchronise");
+    rl_destroy(j);
+    return s ? s : se;
 }
 
 rl_status rl_batch_workspace_bytes(int32_t n_jobs, size_t* bytes) {

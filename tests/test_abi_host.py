@@ -264,6 +264,24 @@ def test_tune_cache_roundtrip(A, tmp_path):
     assert A.rl_tune_lookup(p) is None
 
 
+def test_static_solve_rejects_oversized_jobs_before_device_work(A):
+    """The allocation-free entry point refuses a job whose workspace exceeds its static
+    array with RL_E_NOMEM and a reason, before it touches a device (so this runs without
+    a GPU); graph replay is refused the same way."""
+    L = A.lib()
+    p, keep = _params(A, H=4096, W=4096)
+    st, need = _ws_status(A, p)
+    assert st == A.RL_OK and need > A.RL_STATIC_SCRATCH_BYTES
+    assert L.rl_solve_static(ctypes.byref(p), 10, None, None) == A.RL_E_NOMEM
+    why = A.last_error()
+    assert "rl_solve_static" in why and str(A.RL_STATIC_SCRATCH_BYTES) in why
+    p2, keep2 = _params(A)
+    p2.tuning.graph_iters = 4
+    assert L.rl_solve_static(ctypes.byref(p2), 10, None, None) == A.RL_E_UNSUPPORTED
+    assert L.rl_solve_static(ctypes.byref(p2), -1, None, None) == A.RL_E_INVAL
+    assert L.rl_solve_static(None, 1, None, None) == A.RL_E_INVAL
+
+
 def test_last_error_names_the_reason(A):
     L = A.lib()
     p, keep = _params(A, psf=synth.disc(3), path=A.RL_PATH_BOX_AXIS)
