@@ -754,6 +754,29 @@ def _registry_totals(rows):
     return agg
 
 
+def _last_dispatch_averages(trace_dir, kernels):
+    """Average rocprofv3 duration (us) of the last n dispatches of each registry name,
+    n = the launch count bench.py reports for it, from the per-dispatch kernel trace."""
+    import csv
+    import glob
+    fns = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not fns or not kernels:
+        return {}
+    per = {}
+    for r in csv.DictReader(open(fns[0])):
+        nm = _timing_name(r["Kernel_Name"])
+        if nm:
+            per.setdefault(nm, []).append((int(r["Start_Timestamp"]),
+                                           int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for nm, k in kernels.items():
+        d = sorted(per.get(nm, []))
+        n = int(k["launches"])
+        if len(d) >= n > 0:
+            out[nm] = (n, sum(x[1] for x in d[-n:]) / n / 1e3)
+    return out
+
+
 def summarize_trace(trace_dir, bench_log, command, side=0, workload="batched"):
     """Per-kernel durations from rocprofv3's kernel statistics, next to bench.py's own
     dispatch-event durations of an unprofiled run of the same workload (the benchmark, or
@@ -795,8 +818,8 @@ def summarize_trace(trace_dir, bench_log, command, side=0, workload="batched"):
         for nm in sorted(agg, key=lambda k: -agg[k][1]):
             c, ns = agg[nm]
             out.append(f"| `{nm}` | {c} | {ns / 1e6:.2f} | {ns / c / 1e3:.2f} |")
-    out += ["", "bench.py's own per-kernel durations (dispatch-attached events, same workload, "
-            "same machine, run without the profiler just before):", ""]
+    out += ["", f"bench.py's own per-kernel durations (dispatch-attached HIP events) from the "
+            f"JSON line in `{os.path.basename(bench_log)}`:", ""]
     if side:
         for row in bench.get("rows", []):
             for k, v in row["kernels"].items():
@@ -805,6 +828,16 @@ def summarize_trace(trace_dir, bench_log, command, side=0, workload="batched"):
         return "\n".join(out)
     for k, v in bench.get("kernels", {}).items():
         out.append(f"- `{k}`: {v['avg_us']:.2f} us over {v['launches']} launches")
+    last = _last_dispatch_averages(trace_dir, bench.get("kernels", {}))
+    if last:
+        out += ["", "rocprofv3's durations of the same dispatches bench.py timed with its "
+                "events (the last `launches` dispatches of each name, i.e. bench.py's "
+                "instrumented step):", "",
+                "| Registry name | dispatches | rocprofv3 avg us | bench.py avg us | ratio |",
+                "|---|---|---|---|---|"]
+        for k, (n, us) in last.items():
+            b = bench["kernels"][k]["avg_us"]
+            out.append(f"| `{k}` | {n} | {us:.2f} | {b:.2f} | {us / b:.3f} |")
     rf = bench.get("roofline") or {}
     out += ["", f"Headline of that run: {bench['value']:.4g} {bench['unit']}, "
             f"{bench['ms_per_step']:.3f} ms per step; roofline of `{rf.get('kernel')}`: "
