@@ -115,9 +115,11 @@ def measured_traffic(name, workload="batched"):
 def algorithmic_flops_per_px(kind, info, phase_b):
     """Flops of the paper's algorithm for one output of one phase kernel.
 
-    conv/corr: direct or list filter 2 per tap (multiply-add), generic box filter 2 per
-    run (one add, one subtract per PSF line), 1-D box 2 (Section 3 complexity counts);
-    plus the ratio's division (phase A) or the update's multiplication (phase B)."""
+    conv/corr: direct or list filter 2 per tap (multiply-add; the matrix-core kernel is
+    charged the same, its split products and the zeros of its banded matrices are not
+    algorithmic), generic box filter 2 per run (one add, one subtract per PSF line), 1-D box
+    2 (Section 3 complexity counts); plus the ratio's division (phase A) or the update's
+    multiplication (phase B)."""
     if kind == "slide":
         conv = 2.0 * info["n_spans"]
     elif kind == "rect":
@@ -139,6 +141,8 @@ def job_kind(A, inf):
         return "rect"
     if inf["path"] == A.RL_PATH_BOX_SAT:
         return "sat"
+    if inf["path"] == A.RL_PATH_MFMA:
+        return "mfma"
     return "slide" if inf["lmax"] == 0 else ("direct" if inf["lmax"] == 1 else "span")
 
 
@@ -204,7 +208,8 @@ def roofline_of(kernels, work, traffic_fn):
     return rf
 
 
-KERNEL_NAMES = ["resident_box", "rect_conv_ratio", "rect_corr_update", "sat_conv_ratio",
+KERNEL_NAMES = ["resident_box", "mfma_conv_ratio", "mfma_corr_update", "rect_conv_ratio",
+                "rect_corr_update", "sat_conv_ratio",
                 "sat_corr_update", "slide_conv_ratio", "slide_corr_update", "span_conv_ratio",
                 "span_corr_update", "direct_conv_ratio", "direct_corr_update"]
 
@@ -728,7 +733,7 @@ def report_serving(args, dev):
 def _timing_name(kernel):
     """Map a rocprofv3 kernel symbol to the library's timing-registry name."""
     import re
-    m = re.search(r"rlk::(slide|span|resident|rect|sat|mixed)_kernel<([^>]*)>", kernel)
+    m = re.search(r"rlk::(slide|span|resident|rect|sat|mixed|mfma)_kernel<([^>]*)>", kernel)
     if not m:
         return None
     kind, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]

@@ -70,6 +70,14 @@ typedef int32_t rl_status;
                               from four corners of a table built per LDS tile in FP64, with
                               an exact integer count of non-zero inputs; constant work per
                               pixel; RL_E_UNSUPPORTED when the tile's tables exceed LDS   */
+#define RL_PATH_MFMA 6     /* PSFs with dense lines (the list filter, Section 3, as matrix
+                              products): each PSF row, at most 17 taps wide (at most 64
+                              rows), is a banded matrix applied to 16 x 16 output blocks on
+                              the matrix cores; values and weights are split into three
+                              bfloat16 parts whose six leading products keep float32
+                              accuracy; float32 accumulation.  AUTO picks it where it is
+                              cheaper than the register-blocked spans (dense PSFs); not for
+                              the fused or persistent schedule                            */
 
 /* iteration schedule: how the per-iteration kernels are organised */
 #define RL_SCHED_AUTO 0

@@ -14,11 +14,13 @@ RL_OK, RL_E_INVAL, RL_E_NOMEM, RL_E_DEVICE, RL_E_STATE, RL_E_UNSUPPORTED = 0, -1
 RL_BC_REFLECT, RL_BC_REPLICATE = 0, 1
 RL_PATH_AUTO, RL_PATH_DIRECT, RL_PATH_BOX_AXIS, RL_PATH_RUNS, RL_PATH_BOX_RECT, RL_PATH_BOX_SAT = \
     0, 1, 2, 3, 4, 5
+RL_PATH_MFMA = 6
 RL_SCHED_AUTO, RL_SCHED_TWO_PASS, RL_SCHED_RESIDENT, RL_SCHED_FUSED, RL_SCHED_PERSISTENT = \
     0, 1, 2, 3, 4
 RL_THIN_OFF, RL_THIN_ABS, RL_THIN_REL = 0, 1, 2
 
-PATHS = {"auto": 0, "direct": 1, "box_axis": 2, "runs": 3, "box_rect": 4, "box_sat": 5}
+PATHS = {"auto": 0, "direct": 1, "box_axis": 2, "runs": 3, "box_rect": 4, "box_sat": 5,
+         "mfma": 6}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 SCHEDS = {"auto": 0, "two_pass": 1, "resident": 2, "fused": 3, "persistent": 4}
 SCHED_NAMES = {v: k for k, v in SCHEDS.items()}

@@ -38,7 +38,8 @@ constexpr size_t kSpanPad = 2;  // zero descriptors after each span table (read-
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3, KIND_RECT = 4, KIND_SAT = 5 };
+enum Kind { KIND_SPAN = 0, KIND_SLIDE = 1, KIND_RESIDENT = 2, KIND_FUSED = 3, KIND_RECT = 4, KIND_SAT = 5,
+            KIND_MFMA = 6 };
 
 // ---- kernel timing registry -----------------------------------------------------------
 struct TimedLaunch {
@@ -51,6 +52,7 @@ std::vector<TimedLaunch> g_timed;
 
 struct Config {
     int path = 0, sched = 0, kind = 0, orient = 0, S = 16, lmax = 1;
+    int threads = kNW * 64;  // workgroup size of the phase kernels
     int TA = 64, TB = 64, tiles_a = 1, tiles_b = 1;
     int reach_a = 1, reach_b = 1;  // persistent schedule: tiles within the halo's reach
     // resident
@@ -60,7 +62,7 @@ struct Config {
 };
 
 struct Layout {
-    size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, cnt, plist, tflag, tlist,
+    size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, mf_conv, mf_corr, cnt, plist, tflag, tlist,
         bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, tvg, wt,
         total;
 };
@@ -124,6 +126,64 @@ int next_pow2(int v) {
     return p;
 }
 
+// ---- weight operands of the matrix-core kernel ------------------------------------------
+// bfloat16 of x rounded to nearest (ties to even); x is finite.
+uint16_t bf16_rne(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+int mfma_lines(const rl::OpTable& t) { return t.lane_max - t.lane_min + 1; }
+// one zero line past the end: the kernel loads each line's operands one line ahead
+size_t mfma_table_bytes(const rl::OpTable& t) { return (size_t)(mfma_lines(t) + 1) * 3 * 64 * 16; }
+
+// Per PSF line (lane_min .. lane_max of the ROWS table), per bfloat16 part (w = w1 + w2 + w3,
+// each the rounded remainder of the previous), per lane l: the 8 entries
+// B[8 (l / 16) + t][l % 16] = w(line, c_min + 8 (l / 16) + t - l % 16) of the banded weight
+// operand (zero outside the line's taps).
+std::vector<uint16_t> mfma_table(const rl::OpTable& t) {
+    const int lines = mfma_lines(t), width = t.c_max - t.c_min + 1;
+    std::vector<float> grid((size_t)lines * width, 0.f);
+    for (const rl::Span& s : t.spans)
+        for (int q = 0; q < s.len; ++q)
+            grid[(size_t)(s.lane_off - t.lane_min) * width + (s.c0 + q - t.c_min)] = t.w[s.woff + q];
+    std::vector<uint16_t> out((size_t)(lines + 1) * 3 * 64 * 8, 0);
+    for (int li = 0; li < lines; ++li)
+        for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+                const int dj = 8 * (l / 16) + e - l % 16;
+                const float w = (dj >= 0 && dj < width) ? grid[(size_t)li * width + dj] : 0.f;
+                const uint16_t p1 = bf16_rne(w);
+                const float r1 = w - bf16_value(p1);
+                const uint16_t p2 = bf16_rne(r1);
+                const uint16_t p3 = bf16_rne(r1 - bf16_value(p2));
+                const uint16_t parts[3] = {p1, p2, p3};
+                for (int k = 0; k < 3; ++k) out[(((size_t)li * 3 + k) * 64 + l) * 8 + e] = parts[k];
+            }
+    return out;
+}
+
+// The matrix-core kernel applies to ROWS tables at most MF_MAXW taps wide with at most
+// MF_MAXROWS lines.
+bool mfma_fits(const rl::OpTable& t) {
+    return t.c_max - t.c_min + 1 <= rlk::MF_MAXW && mfma_lines(t) <= rlk::MF_MAXROWS;
+}
+
+// Cost per output in the units of span_cost (VALU ops per output), fitted to measured
+// launch times at 1024^2 and 2048^2 (dense 9 x 9 and 15 x 15, against the span kernel):
+// about 10.5 per PSF line (six products per line, each taking as long per output as one
+// VALU instruction, plus the LDS operand reads they wait on) and 52 for the tile's
+// conversion and the epilogue.
+double mfma_cost(const rl::OpTable& t) { return 10.5 * mfma_lines(t) + 52.0; }
+
 // ---- tuning cache ----------------------------------------------------------------------
 struct TuneKey {
     int path, kh, kw, taps, runs, bucket, thin, schedule;
@@ -181,7 +241,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     const int H = p->height, W = p->width;
     const bool thin = p->thin.mode != RL_THIN_OFF;
     int path = p->path == RL_PATH_AUTO ? c.auto_path : p->path;
-    if (path < RL_PATH_DIRECT || path > RL_PATH_BOX_SAT) { *why = "unknown path"; return RL_E_INVAL; }
+    if (path < RL_PATH_DIRECT || path > RL_PATH_MFMA) { *why = "unknown path"; return RL_E_INVAL; }
     if (path == RL_PATH_BOX_AXIS && !c.is_axis_box) {
         *why = "BOX_AXIS path needs a 1 x L or L x 1 uniform box PSF";
         return RL_E_INVAL;
@@ -293,7 +353,23 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     const int span_S = p->tuning.strip ? p->tuning.strip : def_S;
     const int slide_S = p->tuning.strip ? p->tuning.strip : def_S;
     if (span_S != 4 && span_S != 8 && span_S != 16 && span_S != 32) { *why = "tuning.strip"; return RL_E_INVAL; }
-    if (path == RL_PATH_DIRECT) {
+    const bool mfma_sched = sched == RL_SCHED_AUTO || sched == RL_SCHED_TWO_PASS;
+    if (path == RL_PATH_MFMA) {
+        rl::OpTable t = rl::build_op_table(h, kh, kw, false, rl::Orient::Rows, false, 0);
+        if (!mfma_fits(t)) {
+            *why = "the MFMA path needs PSF rows at most 17 taps wide and at most 64 rows";
+            return RL_E_UNSUPPORTED;
+        }
+        if (!mfma_sched) { *why = "the MFMA path runs on the two-pass schedule"; return RL_E_UNSUPPORTED; }
+    }
+    if (path == RL_PATH_MFMA) {
+        cfg->kind = KIND_MFMA;
+        cfg->orient = rlk::ORIENT_ROWS;
+        cfg->S = 16;
+        cfg->lmax = 0;
+        cfg->conv = rl::build_op_table(h, kh, kw, false, rl::Orient::Rows, false, 0);
+        cfg->corr = rl::build_op_table(h, kh, kw, true, rl::Orient::Rows, false, 0);
+    } else if (path == RL_PATH_DIRECT) {
         cfg->kind = KIND_SPAN;
         cfg->orient = rlk::ORIENT_ROWS;
         cfg->S = std::min(span_S, 16);
@@ -343,14 +419,27 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
                 }
             }
         }
-        rl::Orient o = cfg->orient == 0 ? rl::Orient::Rows : rl::Orient::Cols;
-        bool split = cfg->kind == KIND_SLIDE;
-        int lm = cfg->kind == KIND_SLIDE ? 0 : cfg->lmax;
-        cfg->conv = rl::build_op_table(h, kh, kw, false, o, split, lm);
-        cfg->corr = rl::build_op_table(h, kh, kw, true, o, split, lm);
+        // AUTO: dense lines go to the matrix cores where that is cheaper
+        rl::OpTable mt = rl::build_op_table(h, kh, kw, false, rl::Orient::Rows, false, 0);
+        if (p->path == RL_PATH_AUTO && mfma_sched && mfma_fits(mt) && mfma_cost(mt) < best) {
+            cfg->path = RL_PATH_MFMA;
+            cfg->kind = KIND_MFMA;
+            cfg->orient = rlk::ORIENT_ROWS;
+            cfg->S = 16;
+            cfg->lmax = 0;
+            cfg->conv = mt;
+            cfg->corr = rl::build_op_table(h, kh, kw, true, rl::Orient::Rows, false, 0);
+        } else {
+            rl::Orient o = cfg->orient == 0 ? rl::Orient::Rows : rl::Orient::Cols;
+            bool split = cfg->kind == KIND_SLIDE;
+            int lm = cfg->kind == KIND_SLIDE ? 0 : cfg->lmax;
+            cfg->conv = rl::build_op_table(h, kh, kw, false, o, split, lm);
+            cfg->corr = rl::build_op_table(h, kh, kw, true, o, split, lm);
+        }
     }
     cfg->TA = 64;
-    cfg->TB = kNW * cfg->S;
+    cfg->TB = cfg->kind == KIND_MFMA ? rlk::MF_T : kNW * cfg->S;
+    if (cfg->kind == KIND_MFMA) cfg->threads = rlk::MF_NW * 64;
     const int extra = 0;  // windows never read past the last tap of a piece
     auto lds_for = [&](const rl::OpTable& t) {
         size_t b = tile_lds_bytes(t, cfg->orient, cfg->TB, extra);
@@ -371,6 +460,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             int ny = 64 + t.lane_max - t.lane_min, nx = cfg->TB + t.c_max - t.c_min;
             b = rlk::sat_lds_bytes<kNW>(ny, nx);
         }
+        if (cfg->kind == KIND_MFMA) b = rlk::mfma_lds_bytes(mfma_lines(t));  // three bf16 planes
         return b;
     };
     cfg->lds_a = lds_for(cfg->conv);
@@ -430,6 +520,10 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     L.conv_w = take((cfg.conv.w.size() + pad) * 4);
     L.corr_spans = take((cfg.corr.spans.size() + kSpanPad) * sizeof(DevSpan));
     L.corr_w = take((cfg.corr.w.size() + pad) * 4);
+    if (cfg.kind == KIND_MFMA) {
+        L.mf_conv = take(mfma_table_bytes(cfg.conv));
+        L.mf_corr = take(mfma_table_bytes(cfg.corr));
+    }
     const size_t ntiles = (size_t)cfg.tiles_a * cfg.tiles_b;
     if (thin) {
         L.cnt = take(N);
@@ -491,6 +585,7 @@ struct rl_job {
     bool live;
     std::vector<DevSpan> h_conv, h_corr;
     std::vector<float> h_conv_w, h_corr_w;
+    std::vector<uint16_t> h_mf_conv, h_mf_corr;  // matrix-core weight operands (bf16 bits)
     PhaseArgs h_args[2];
     int32_t h_prefix[2];
     rlk::FusedArgs h_fargs;
@@ -664,6 +759,7 @@ std::atomic<int> g_spin_limit{kSpinLimit};  // rl_debug_spin_limit changes it fo
 rl_status check_persist_abort(rl_job* j, hipStream_t s);
 
 PhaseFn phase_fn(const Config& c, bool phase_b) {
+    if (c.kind == KIND_MFMA) return phase_b ? rlk::mfma_kernel<true> : rlk::mfma_kernel<false>;
     if (c.kind == KIND_RECT) {
         if (c.S == 4) return phase_b ? rlk::rect_kernel<4, kNW, true> : rlk::rect_kernel<4, kNW, false>;
         if (c.S == 8) return phase_b ? rlk::rect_kernel<8, kNW, true> : rlk::rect_kernel<8, kNW, false>;
@@ -687,6 +783,7 @@ PhaseFn phase_fn(const Config& c, bool phase_b) {
 }
 
 const char* phase_name(const Config& c, bool phase_b) {
+    if (c.kind == KIND_MFMA) return phase_b ? "mfma_corr_update" : "mfma_conv_ratio";
     if (c.kind == KIND_RECT) return phase_b ? "rect_corr_update" : "rect_conv_ratio";
     if (c.kind == KIND_SAT) return phase_b ? "sat_corr_update" : "sat_conv_ratio";
     if (c.kind == KIND_SPAN)
@@ -726,6 +823,8 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     a.u = j->at<float>(j->L.u);
     a.spans = phase_b ? j->at<DevSpan>(j->L.corr_spans) : j->at<DevSpan>(j->L.conv_spans);
     a.wts = phase_b ? j->at<float>(j->L.corr_w) : j->at<float>(j->L.conv_w);
+    if (c.kind == KIND_MFMA)  // the banded bfloat16 weight operands
+        a.wts = phase_b ? j->at<float>(j->L.mf_corr) : j->at<float>(j->L.mf_conv);
     a.n_spans = (int32_t)t.spans.size();
     a.lane_min = t.lane_min;
     a.lane_max = t.lane_max;
@@ -1008,7 +1107,7 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
         la.kb = lb.kb = j->k;
         if (thin) la.one.list_ok = lb.one.list_ok = use_tile_list(j) ? 1 : 0;
         if (rl_status tst = enqueue_tv(j, s)) return tst;
-        rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(kNW * 64), c.lds_a, s, la), na);
+        rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(c.threads), c.lds_a, s, la), na);
         if (st) return st;
         if (j->p.rob_eps > 0.f) {
             // robust variant: weights and weighted ratio from v, then h^* * w into the
@@ -1024,10 +1123,10 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
             lw.one.src = wt;
             lw.one.store = j->at<float>(j->L.tvg);
             lw.one.tvg = nullptr;
-            st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lw), nbn);
+            st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(c.threads), c.lds_b, s, lw), nbn);
             if (st) return st;
         }
-        st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(kNW * 64), c.lds_b, s, lb), nbn);
+        st = dev_err(launch(nbn, fb, dim3(ntiles), dim3(c.threads), c.lds_b, s, lb), nbn);
         if (st) return st;
         j->k += 1;
         if (thin) j->pending_finalize = true;
@@ -1124,6 +1223,11 @@ std::vector<TuneEntry> tune_candidates(const rl_params* p, const Config& base) {
         return v;
     }
     const int gi = thin ? 0 : 16;
+    if (base.kind == KIND_MFMA) {  // no strip length to choose
+        add(RL_SCHED_TWO_PASS, 0, 0, 0, 0);
+        if (gi) add(RL_SCHED_TWO_PASS, 0, 0, 0, gi);
+        return v;
+    }
     for (int strip : {4, 8, 16}) {
         add(RL_SCHED_TWO_PASS, strip, 0, 0, 0);
         if (gi) add(RL_SCHED_TWO_PASS, strip, 0, 0, gi);
@@ -1226,6 +1330,12 @@ rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, 
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_spans), j->h_corr.data(), j->h_corr.size() * sizeof(DevSpan), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.conv_w), j->h_conv_w.data(), j->h_conv_w.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_w), j->h_corr_w.data(), j->h_corr_w.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && j->cfg.kind == KIND_MFMA) {
+        j->h_mf_conv = mfma_table(j->cfg.conv);
+        j->h_mf_corr = mfma_table(j->cfg.corr);
+        e = hipMemcpyAsync(j->at<void>(j->L.mf_conv), j->h_mf_conv.data(), j->h_mf_conv.size() * 2, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.mf_corr), j->h_mf_corr.data(), j->h_mf_corr.size() * 2, hipMemcpyHostToDevice, s);
+    }
     if ((st = dev_err(e, "upload PSF"))) { delete j; return st; }
     if (j->cfg.kind == KIND_FUSED) {
         rlk::FusedArgs& a = j->h_fargs;
@@ -1474,6 +1584,7 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         std::vector<int32_t> prefix;
         size_t off_a, off_b, off_p;
         size_t lds_a = 0, lds_b = 0;
+        int threads = kNW * 64;
         PhaseFn fa, fb;
         const char *na, *nb;
     };
@@ -1492,6 +1603,7 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
             g.lds_b = std::max(g.lds_b, c.lds_b);
         }
         const Config& c0 = jobs[g.idx[0]]->cfg;
+        g.threads = c0.threads;
         g.fa = phase_fn(c0, false);
         g.fb = phase_fn(c0, true);
         g.na = phase_name(c0, false);
@@ -1581,7 +1693,7 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
                     if (j1->p.thin.mode != RL_THIN_OFF) la.one.list_ok = use_tile_list(j1) ? 1 : 0;
                 }
                 st = dev_err(launch(phase ? g.nb : g.na, phase ? g.fb : g.fa, dim3(g.prefix[m]),
-                                    dim3(kNW * 64), phase ? g.lds_b : g.lds_a, gsm, la),
+                                    dim3(g.threads), phase ? g.lds_b : g.lds_a, gsm, la),
                              phase ? g.nb : g.na);
                 if (st) return st;
             }

@@ -660,6 +660,147 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Matrix-core kernel for PSFs with dense lines (the list filter, Section 3, evaluated as
+// matrix products).  For one PSF line di, the correlation over a 16 x 16 output block is a
+// product with a banded matrix:
+//     out[m][n] += sum_{c < 32} A[m][c] * B[c][n],
+//     A[m][c] = src(y0 + m + di, x0 + c_min + c),   B[c][n] = w(di, c_min + c - n)
+// (B is zero outside the line's taps; lines are at most MF_MAXW taps wide), one
+// v_mfma_f32_16x16x32_bf16 per line and block.  Float32 accuracy is kept by splitting every
+// source value and weight into three bfloat16 parts, x = x1 + x2 + x3 (each part the
+// rounded remainder of the previous; exact for float32 inputs), and forming the six products
+// x_i w_j with i + j <= 4: the three dropped ones are below 2^-24 of the full product, and a
+// product of two bfloat16 values is exact in float32.  The leading products x1 w1 of even
+// and odd lines go into two accumulators, the five smaller ones into a third; the output is
+// (even + odd) + small.  A window whose inputs are all zero gives exactly zero.
+//
+// A workgroup of MF_NW wavefronts owns a 64 x 64 output tile; wavefront w computes rows
+// 16 w .. 16 w + 15 as four 16 x 16 blocks side by side, which share each line's weight
+// operand.  The source tile (PSF halo included, boundary fold applied) is converted once
+// into three bfloat16 planes in LDS with a row pitch of MF_PITCH elements (11 x 16 bytes):
+// the 16 rows that a 16-lane group reads with one 16-byte load start in distinct bank
+// quadruples.  Operand layout of v_mfma_f32_16x16x32_bf16 on a wavefront of 64: lane l
+// holds A[l % 16][8 (l / 16) + t] and B[8 (l / 16) + t][l % 16] for t < 8 and receives
+// D[4 (l / 16) + t][l % 16] for t < 4.  The weight operands (per line, per part, per lane:
+// 8 bfloat16 values) are built on the host; p.wts points to them.  The epilogue is the
+// one of the other phase kernels (ratio or update, thinning counters, TV, robust store).
+// ---------------------------------------------------------------------------------------
+constexpr int MF_NW = 4;
+constexpr int MF_T = 64;             // tile rows and columns
+constexpr int MF_NX = MF_T + 16;     // LDS columns: the last block reads 16 * 3 + 32
+constexpr int MF_PITCH = 88;         // LDS row pitch in bfloat16 elements
+constexpr int MF_MAXW = 17;          // widest PSF line (16 + MF_MAXW - 1 <= 32)
+constexpr int MF_MAXROWS = 64;       // most PSF lines
+constexpr int MF_SPITCH = 84;        // row pitch (floats) of the float32 staging tile
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr size_t mfma_lds_bytes(int lines) {
+    return (size_t)(MF_T + lines - 1) * (3 * MF_PITCH * 2 + MF_SPITCH * 4);
+}
+
+__device__ __forceinline__ void split3(float x, __bf16& p1, __bf16& p2, __bf16& p3) {
+    p1 = (__bf16)x;
+    const float r1 = x - (float)p1;
+    p2 = (__bf16)r1;
+    p3 = (__bf16)(r1 - (float)p2);
+}
+
+template <bool PHASE_B>
+__global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
+    extern __shared__ float lds_f[];
+    __bf16* lds = reinterpret_cast<__bf16*>(lds_f);
+    int a0, b0;
+    PhaseArgs p;
+    if (!resolve<PHASE_B>(L, p, MF_T, MF_T, a0, b0)) return;
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    const int m = lane & 15, q = lane >> 4;
+    const int lines = p.lane_max - p.lane_min + 1;
+    const int ny = MF_T + lines - 1;
+    const int plane = ny * MF_PITCH;
+
+    // epilogue inputs of this lane's 16 outputs, loaded before the tile so they overlap it
+    EpiIn ein[4][4];
+#pragma unroll
+    for (int bx = 0; bx < 4; ++bx)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int y = a0 + 16 * wv + 4 * q + t, x = b0 + 16 * bx + m;
+            if (y < p.H && x < p.W) ein[bx][t] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+        }
+
+    // source tile: float32 into LDS by DMA (load_tile: every row chunk in flight at once,
+    // boundary fold applied to the addresses), then converted in LDS into the three bfloat16
+    // planes, four consecutive values per thread and step
+    const int ly0 = a0 + p.lane_min, lx0 = b0 + p.c_min;
+    float* stage = reinterpret_cast<float*>(lds + 3 * plane);
+    load_tile(stage, p.src, p.H, p.W, p.bc, ly0, lx0, ny, MF_NX, MF_SPITCH);
+    lds_dma_wait();
+    __syncthreads();
+    for (int g = threadIdx.x; g < ny * (MF_NX / 4); g += MF_NW * 64) {
+        const int row = g / (MF_NX / 4), c4 = 4 * (g - row * (MF_NX / 4));
+        const float4 x = *reinterpret_cast<const float4*>(stage + row * MF_SPITCH + c4);
+        __bf16 a[4], b[4], c[4];
+        split3(x.x, a[0], b[0], c[0]);
+        split3(x.y, a[1], b[1], c[1]);
+        split3(x.z, a[2], b[2], c[2]);
+        split3(x.w, a[3], b[3], c[3]);
+        __bf16* d = lds + row * MF_PITCH + c4;
+        __builtin_memcpy(d, a, 8);
+        __builtin_memcpy(d + plane, b, 8);
+        __builtin_memcpy(d + 2 * plane, c, 8);
+    }
+    __syncthreads();
+
+    f32x4 even[4], odd[4], small[4];
+#pragma unroll
+    for (int bx = 0; bx < 4; ++bx)
+        for (int t = 0; t < 4; ++t) even[bx][t] = odd[bx][t] = small[bx][t] = 0.f;
+    // weight operands: each line's are loaded one line ahead (the table carries one zero
+    // line past its end), so their round trip overlaps the previous line's products
+    const bf16x8* tab = reinterpret_cast<const bf16x8*>(p.wts);
+    bf16x8 nw1 = tab[lane], nw2 = tab[64 + lane], nw3 = tab[128 + lane];
+    const __bf16* base = lds + (16 * wv + m) * MF_PITCH + 8 * q;
+    for (int di = 0; di < lines; ++di) {
+        const bf16x8 w1 = nw1, w2 = nw2, w3 = nw3;
+        nw1 = tab[(3 * di + 3) * 64 + lane];
+        nw2 = tab[(3 * di + 4) * 64 + lane];
+        nw3 = tab[(3 * di + 5) * 64 + lane];
+        const __bf16* rp = base + di * MF_PITCH;
+        const bool odd_line = (di & 1) != 0;
+#pragma unroll
+        for (int bx = 0; bx < 4; ++bx) {
+            const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(rp + 16 * bx);
+            const bf16x8 x2 = *reinterpret_cast<const bf16x8*>(rp + plane + 16 * bx);
+            const bf16x8 x3 = *reinterpret_cast<const bf16x8*>(rp + 2 * plane + 16 * bx);
+            if (odd_line) odd[bx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w1, odd[bx], 0, 0, 0);
+            else even[bx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w1, even[bx], 0, 0, 0);
+            f32x4 sm = small[bx];
+            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w2, sm, 0, 0, 0);
+            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, w1, sm, 0, 0, 0);
+            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w3, sm, 0, 0, 0);
+            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, w2, sm, 0, 0, 0);
+            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x3, w1, sm, 0, 0, 0);
+            small[bx] = sm;
+        }
+    }
+
+    int n_active = 0;
+#pragma unroll
+    for (int bx = 0; bx < 4; ++bx)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int y = a0 + 16 * wv + 4 * q + t, x = b0 + 16 * bx + m;
+            const float v = (even[bx][t] + odd[bx][t]) + small[bx][t];
+            int act = 0;
+            if (y < p.H && x < p.W) act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, ein[bx][t], v);
+            if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+        }
+    if (PHASE_B) add_active(p, n_active);
+}
+
+// ---------------------------------------------------------------------------------------
 // Sliding kernel (generic box filter): every span is a run of equal weights.  Moving the
 // output one step along the strip adds the entering tap and removes the leaving tap of each
 // run, 2 operations per run per output.  The workgroup's NW wavefronts cover consecutive

@@ -44,6 +44,8 @@ def test_timing_names():
     assert n("void rlk::rect_kernel<8, 8, false>(rlk::LaunchArgs)") == "rect_conv_ratio"
     assert n("void rlk::sat_kernel<4, 8, true>(rlk::LaunchArgs)") == "sat_corr_update"
     assert n("void rlk::resident_kernel<1, 8>(rlk::ResidentArgs)") == "resident_box"
+    assert n("void rlk::mfma_kernel<true>(rlk::LaunchArgs)") == "mfma_corr_update"
+    assert n("void rlk::mfma_kernel<false>(rlk::LaunchArgs)") == "mfma_conv_ratio"
     assert n("__amd_rocclr_copyBuffer") is None
 
 
@@ -106,7 +108,7 @@ def test_pooled_traffic_over_template_instances(tmp_path):
 
 
 class _FakeAbi:
-    RL_SCHED_RESIDENT, RL_PATH_BOX_RECT, RL_PATH_BOX_SAT = 2, 4, 5
+    RL_SCHED_RESIDENT, RL_PATH_BOX_RECT, RL_PATH_BOX_SAT, RL_PATH_MFMA = 2, 4, 5, 6
 
 
 def test_roofline_accounting():
