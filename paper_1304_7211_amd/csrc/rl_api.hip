@@ -1155,6 +1155,28 @@ hipStream_t g_side[kSideStreams] = {};
 hipEvent_t g_fork = nullptr;
 hipEvent_t g_join[kSideStreams] = {};
 
+// Side streams the batch spreads its kernel groups over.
+constexpr int kBatchStreams = 8;
+static_assert(kBatchStreams <= kSideStreams, "batch streams");
+
+// Estimated microseconds per output of a two-pass phase launch per unit of this cost (the
+// span_cost units), and per launch, from launch times measured at 1024^2 and 2048^2.
+double unit_cost(const Config& c) {
+    switch (c.kind) {
+        case KIND_SPAN: return span_cost(c.conv, c.S, c.lmax, true);
+        case KIND_SLIDE: return slide_cost(c.conv, c.S, true);
+        case KIND_MFMA: return mfma_cost(c.conv);
+        default: return 40.0;
+    }
+}
+
+// Estimated microseconds of a job's launches outside the tiled groups: resident lines
+// (about 4.2 ns per pixel-iteration at 1 Mpx), fused and robust jobs as two-pass ones.
+double resident_work_us(const rl_job* j, int32_t n) {
+    if (j->cfg.kind == KIND_RESIDENT) return 10.0 + 4.2e-6 * (double)j->N * n;
+    return n * (20.0 + 5.8e-8 * 60.0 * (double)j->N);
+}
+
 rl_status side_streams(int n) {
     std::lock_guard<std::mutex> lk(g_smu);
     rl_status st;
@@ -1588,13 +1610,40 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         PhaseFn fa, fb;
         const char *na, *nb;
     };
+    // estimated work (us) of each job; a variant group whose work exceeds a share of the
+    // whole batch is cut into several groups (consecutive in iteration order, so each stays
+    // ordered by remaining iterations), so that no single chain of dependent launches
+    // outlasts the others by much
+    std::vector<double> work(n_jobs, 0.0);
+    double total_work = 0.0;
+    for (int i : tiled) {
+        work[i] = 5.8e-8 * unit_cost(jobs[i]->cfg) * (double)jobs[i]->N * n_iter[i] + 20.0 * n_iter[i] / 8.0;
+        total_work += work[i];
+    }
+    for (int i : resident) total_work += resident_work_us(jobs[i], n_iter[i]);
+    const double share = total_work / (2.0 * kBatchStreams);
+    std::vector<std::vector<int>> chunks;
+    for (auto& kv : groups) {
+        std::vector<int> v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return n_iter[a] > n_iter[b]; });
+        std::vector<int> cur;
+        double acc = 0.0;
+        for (int i : v) {
+            cur.push_back(i);
+            acc += work[i];
+            if (acc >= share) {
+                chunks.push_back(cur);
+                cur.clear();
+                acc = 0.0;
+            }
+        }
+        if (!cur.empty()) chunks.push_back(cur);
+    }
     std::vector<G> gs;
     size_t off = 0;
-    for (auto& kv : groups) {
+    for (auto& chunk : chunks) {
         G g;
-        g.idx = kv.second;
-        std::stable_sort(g.idx.begin(), g.idx.end(),
-                         [&](int a, int b) { return n_iter[a] > n_iter[b]; });
+        g.idx = chunk;
         g.prefix.push_back(0);
         for (int i : g.idx) {
             const Config& c = jobs[i]->cfg;
@@ -1645,21 +1694,42 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         if ((st = dev_err(e, "batch tables"))) return st;
         bs.pending = true;
     }
-    // fork: every group (and the resident jobs) gets its own stream after the table copy
-    const int n_streams = std::min<int>(kSideStreams, (int)gs.size() + (resident.empty() ? 0 : 1));
+    // fork: the kernel groups and the resident jobs are spread over kBatchStreams side
+    // streams (no more than the device's hardware queues, so that streams do not share a
+    // queue and serialise behind each other), longest estimated work first, each to the
+    // stream with the least work so far
+    std::vector<std::pair<double, int>> items;  // (estimated us, group index or -1 - job)
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+        double w = 20.0 * n_iter[gs[gi].idx[0]];
+        for (int i : gs[gi].idx) w += 5.8e-8 * unit_cost(jobs[i]->cfg) * (double)jobs[i]->N * n_iter[i];
+        items.emplace_back(w, (int)gi);
+    }
+    for (int i : resident) items.emplace_back(resident_work_us(jobs[i], n_iter[i]), -1 - i);
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+    const int n_streams = std::min<int>(kBatchStreams, (int)items.size());
+    std::vector<double> load(n_streams, 0.0);
+    std::vector<int> group_stream(gs.size(), 0);
+    std::vector<std::pair<int, int>> resident_stream;  // (job, stream)
+    for (const auto& it : items) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[q] += it.first;
+        if (it.second >= 0) group_stream[it.second] = q;
+        else resident_stream.emplace_back(-1 - it.second, q);
+    }
     if ((st = side_streams(n_streams))) return st;
     std::lock_guard<std::mutex> lk(g_smu);
     if ((st = dev_err(hipEventRecord(g_fork, s), "fork"))) return st;
     for (int q = 0; q < n_streams; ++q)
         if ((st = dev_err(hipStreamWaitEvent(g_side[q], g_fork, 0), "fork wait"))) return st;
-    auto stream_of_group = [&](size_t gi) { return g_side[gi % n_streams]; };
+    auto stream_of_group = [&](size_t gi) { return g_side[group_stream[gi]]; };
     // jobs on the resident schedule run all their iterations in one launch each; fused
-    // jobs one launch per iteration, on the same side stream
-    for (int i : resident) {
-        rl_job* j = jobs[i];
+    // jobs one launch per iteration, on their side stream
+    for (const auto& rq : resident_stream) {
+        rl_job* j = jobs[rq.first];
         hipStream_t keep = j->stream;
-        j->stream = g_side[n_streams - 1];
-        st = enqueue_iterations(j, n_iter[i]);
+        j->stream = g_side[rq.second];
+        st = enqueue_iterations(j, n_iter[rq.first]);
         j->stream = keep;
         if (st) return st;
     }
