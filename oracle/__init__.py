@@ -14,7 +14,9 @@ is the ctypes shim plus two pieces of pure-Python definition:
 Function index (each cites the passage it follows):
   conv, corr          Section 1 eq. 2 (u*h) and Section 2 eq. 3 (h^* * r)
   rl                  Section 2 eq. 3, u^0 = f
-  thin_step, rl_thin  Section 4 eq. 4-5 and the every-ten-iterations reset
+  thin_step, rl_thin  Section 4 eq. 4-5 and the every-ten-iterations reset; with
+                      thin["block"] > 1 the block rule (freeze decisions per tile), a
+                      refinement of Section 4's adaptive rule
   below               Section 4 convergence test (float32 decision)
 """
 import ctypes
@@ -75,6 +77,12 @@ def _load(mutant=0):
                                          ctypes.c_int, ctypes.c_int, ctypes.c_long,
                                          ctypes.c_int, ctypes.c_float, ctypes.c_int,
                                          ctypes.c_int, dp]
+        lib.oracle_thin_step_blocks.restype = ctypes.c_long
+        lib.oracle_thin_step_blocks.argtypes = [dp, dp, dp, ctypes.POINTER(ctypes.c_uint8),
+                                                ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, ctypes.c_long,
+                                                ctypes.c_int, ctypes.c_float, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, dp]
         lib.oracle_below.restype = ctypes.c_int
         lib.oracle_below.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                      ctypes.c_float]
@@ -228,11 +236,35 @@ class Oracle:
         assert u.flags.c_contiguous and r.flags.c_contiguous and cnt.flags.c_contiguous
         work = np.empty((H, W), dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
+        block = int(thin.get("block", 0))
+        if block > 1:  # block rule: freeze decisions per block x block tile
+            return int(self.lib.oracle_thin_step_blocks(
+                fp, u.ctypes.data_as(dp), r.ctypes.data_as(dp),
+                cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), H, W, hp, hd.shape[0],
+                hd.shape[1], BC[bc], int(k), THIN[thin["mode"]], float(np.float32(thin["tau"])),
+                int(thin["hysteresis"]), int(thin["reset_period"]), block,
+                work.ctypes.data_as(dp)))
         return int(self.lib.oracle_thin_step(
             fp, u.ctypes.data_as(dp), r.ctypes.data_as(dp),
             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), H, W, hp, hd.shape[0],
             hd.shape[1], BC[bc], int(k), THIN[thin["mode"]], float(np.float32(thin["tau"])),
             int(thin["hysteresis"]), int(thin["reset_period"]), work.ctypes.data_as(dp)))
+
+    def thin_step_blocks(self, f, u, r, cnt, h, k, thin, block, bc="reflect"):
+        """One thinned iteration under the block rule with the given block size (block = 1
+        calls the block code with 1 x 1 blocks, for the check against the per-pixel rule)."""
+        H, W = f.shape
+        fd, fp = self._d(f)
+        hd, hp = self._d(h)
+        assert u.dtype == np.float64 and r.dtype == np.float64 and cnt.dtype == np.uint8
+        work = np.empty((H, W), dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        return int(self.lib.oracle_thin_step_blocks(
+            fp, u.ctypes.data_as(dp), r.ctypes.data_as(dp),
+            cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), H, W, hp, hd.shape[0],
+            hd.shape[1], BC[bc], int(k), THIN[thin["mode"]], float(np.float32(thin["tau"])),
+            int(thin["hysteresis"]), int(thin["reset_period"]), int(block),
+            work.ctypes.data_as(dp)))
 
     def rl_thin(self, f, h, K, thin, bc="reflect", u0=None, keep_lists=False,
                 callback=None):

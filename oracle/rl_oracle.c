@@ -377,6 +377,83 @@ long oracle_thin_step(const double *f, double *u, double *r, uint8_t *cnt, int H
     return n_active;
 }
 
+/*
+ * One thinned RL iteration k under the block rule (a refinement of the adaptive update rule
+ * of Section 4, which leaves such rules open): the image is cut into B x B blocks aligned
+ * at (0, 0) (the last ones cut by the image edge), and the decision to freeze is taken per
+ * block.  Block t's counter is the counter of its top-left pixel.
+ *   full  = (k == 0) or (R > 0 and k mod R == 0): every block is active;
+ *   else  block t is active iff its counter < hyst.
+ * Every pixel of an active block is active: r = f / (u^k*h) (guarded), then
+ * u^{k+1} = u^k . (h^* * r), where pixels of frozen blocks contribute their stale r.  Then
+ * the block's counter becomes min(c+1, 255) if the float32 convergence test holds for
+ * every one of its pixels, else 0.  Frozen blocks keep u and r.  On return every pixel of
+ * every block carries its block's counter.  B = 1 is the per-pixel rule above.
+ * Returns the number of active pixels.
+ */
+long oracle_thin_step_blocks(const double *f, double *u, double *r, uint8_t *cnt, int H,
+                             int W, const double *h, int kh, int kw, int bc, long k, int mode,
+                             float tau, int hyst, int reset_period, int B, double *u_prev)
+{
+    const long N = (long)H * W;
+    const int full = (k == 0) || (reset_period > 0 && k % reset_period == 0);
+    const int TY = (H + B - 1) / B, TX = (W + B - 1) / B;
+    const long NT = (long)TY * TX;
+    uint8_t *tc = (uint8_t *)malloc((size_t)NT);
+    uint8_t *act = (uint8_t *)malloc((size_t)NT);
+    uint8_t *all = (uint8_t *)malloc((size_t)NT);
+    for (int ty = 0; ty < TY; ++ty)
+        for (int tx = 0; tx < TX; ++tx) {
+            long t = (long)ty * TX + tx;
+            tc[t] = cnt[(long)ty * B * W + (long)tx * B];
+            act[t] = (uint8_t)(full || tc[t] < hyst);
+            all[t] = 1;
+        }
+    long n_active = 0;
+    for (long p = 0; p < N; ++p) {
+        u_prev[p] = u[p];
+        if (act[(p / W / B) * TX + (p % W) / B]) ++n_active;
+    }
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x)
+            if (act[(y / B) * TX + x / B])
+                r[y * W + x] = ratio(f[y * W + x], conv_at(u_prev, H, W, h, kh, kw, bc, y, x));
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x)
+            if (act[(y / B) * TX + x / B])
+                u[y * W + x] = update(u_prev[y * W + x], corr_at(r, H, W, h, kh, kw, bc, y, x));
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            long t = (y / B) * TX + x / B, p = y * W + x;
+            if (!act[t]) continue;
+#if ORACLE_MUTANT == 12
+            /* planted: a block freezes when any one of its pixels passes the test */
+            if (all[t] == 1) all[t] = 0;
+            if (oracle_below((float)u[p], (float)u_prev[p], mode, tau)) all[t] = 2;
+#else
+            if (!(mode != THIN_OFF && oracle_below((float)u[p], (float)u_prev[p], mode, tau)))
+                all[t] = 0;
+#endif
+        }
+    for (long t = 0; t < NT; ++t)
+        if (act[t]) {
+#if ORACLE_MUTANT == 12
+            const int pass = all[t] == 2;
+#else
+            const int pass = all[t] != 0 && mode != THIN_OFF;
+#endif
+            tc[t] = pass ? (uint8_t)(tc[t] < 255 ? tc[t] + 1 : 255) : 0;
+        }
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) cnt[y * W + x] = tc[(y / B) * TX + x / B];
+    free(tc);
+    free(act);
+    free(all);
+    return n_active;
+}
+
 /* The convergence test above applied to n pairs (a[i], b[i]); out[i] = 0 or 1. */
 void oracle_below_many(const float *a, const float *b, long n, int mode, float tau,
                        uint8_t *out)

@@ -26,6 +26,9 @@ void oracle_rl_robust(const double *f, double *u, int H, int W, const double *h,
 long oracle_thin_step(const double *f, double *u, double *r, uint8_t *cnt, int H, int W,
                       const double *h, int kh, int kw, int bc, long k, int mode, float tau,
                       int hyst, int reset_period, double *u_prev);
+long oracle_thin_step_blocks(const double *f, double *u, double *r, uint8_t *cnt, int H,
+                             int W, const double *h, int kh, int kw, int bc, long k, int mode,
+                             float tau, int hyst, int reset_period, int B, double *u_prev);
 double oracle_sum(const double *a, long n);
 
 static void put(const char *name, const double *a, long n)
@@ -74,6 +77,17 @@ int main(void)
     for (long i = 0; i < n; ++i) a[i] = cnt[i];
     put("thin_cnt", a, n);
     put("thin_active", act, ks);
+
+    memcpy(u, f, sizeof(double) * n);
+    memset(r, 0, sizeof(double) * n);
+    memset(cnt, 0, (size_t)n);
+    for (int k = 0; k < ks; ++k)
+        act[k] = (double)oracle_thin_step_blocks(f, u, r, cnt, H, W, h, kh, kw, bc, k, mode,
+                                                 tau, hyst, R, 3, a);
+    put("block_u", u, n);
+    for (long i = 0; i < n; ++i) a[i] = cnt[i];
+    put("block_cnt", a, n);
+    put("block_active", act, ks);
 
     memcpy(u, f, sizeof(double) * n);
     oracle_rl_tv(f, u, H, W, h, kh, kw, bc, K, 0.1, 1e-3, r, a);

@@ -260,6 +260,100 @@ def test_thin_step_frozen_pixels(orc, bc, mode, k):
         assert 0 < np.count_nonzero(c[active] == 0) < active.sum()
 
 
+# ---- thinned step under the block rule (freeze decisions per B x B block) ------------------
+def _block_state(shape, B, hyst, seed):
+    """A seeded mid-run state whose counters are constant on B x B blocks: some blocks
+    frozen (cnt >= hyst), the others active."""
+    rng = np.random.default_rng(seed)
+    H, W = shape
+    f = rng.uniform(0.05, 1.0, shape)
+    u = rng.uniform(0.1, 1.0, shape)
+    r = rng.uniform(0.5, 1.5, shape)
+    TY, TX = -(-H // B), -(-W // B)
+    tc = np.where(rng.random((TY, TX)) < 0.4, rng.integers(hyst, 60, (TY, TX)),
+                  rng.integers(0, hyst, (TY, TX))).astype(np.uint8)
+    cnt = np.kron(tc, np.ones((B, B), np.uint8))[:H, :W].copy()
+    return f, u, r, cnt, tc
+
+
+def _block_step_expected(f, u_prev, r_old, tc, B, h, thin, mode, full):
+    """The block rule written with scipy: every pixel of an active block gets a fresh ratio
+    and update (computed with the stale ratio of frozen blocks); a block's counter counts up
+    only if the float32 test holds on all of its pixels."""
+    H, W = f.shape
+    tact = np.ones(tc.shape, bool) if full else tc < thin["hysteresis"]
+    active = np.kron(tact, np.ones((B, B), bool))[:H, :W]
+    h64 = h.astype(np.float64)
+    v = ndimage.convolve(u_prev, h64, mode=mode)
+    r_mixed = np.where(active, np.where(v > 0, f / np.where(v > 0, v, 1.0), 0.0), r_old)
+    u_new = np.where(active, u_prev * ndimage.correlate(r_mixed, h64, mode=mode), u_prev)
+    a32, b32 = u_new.astype(np.float32), u_prev.astype(np.float32)
+    d = np.abs((a32 - b32).astype(np.float32))
+    t = (np.float32(thin["tau"]) * b32).astype(np.float32) if thin["mode"] == "rel" \
+        else np.float32(thin["tau"])
+    below = (d < t) | ((a32 == 0) & (b32 == 0))
+    tc_new = tc.copy()
+    for ty in range(tc.shape[0]):
+        for tx in range(tc.shape[1]):
+            if tact[ty, tx]:
+                ok = below[ty * B:(ty + 1) * B, tx * B:(tx + 1) * B].all()
+                tc_new[ty, tx] = min(int(tc[ty, tx]) + 1, 255) if ok else 0
+    cnt = np.kron(tc_new, np.ones((B, B), np.uint8))[:H, :W]
+    return u_new, r_mixed, cnt, active
+
+
+@pytest.mark.parametrize("bc,mode", [("reflect", "reflect"), ("replicate", "nearest")])
+@pytest.mark.parametrize("k", [13, 20])
+def test_block_rule_step(orc, bc, mode, k):
+    B = 4
+    # a large tau so that both block decisions occur on random data
+    thin = dict(mode="rel", tau=0.25, hysteresis=3, reset_period=10, compact_period=10,
+                block=B)
+    for h in (synth.disc(2), synth.oblique_line(9, 30.0)):
+        f, u0, r0, c0, tc = _block_state((23, 30), B, thin["hysteresis"], 91 + k)
+        full = oracle.is_full(k, thin["reset_period"])
+        want_u, want_r, want_c, active = _block_step_expected(f, u0, r0, tc, B, h, thin,
+                                                               mode, full)
+        u, r, c = u0.copy(), r0.copy(), c0.copy()
+        n = orc.thin_step(f, u, r, c, h, k, thin, bc)
+        assert n == int(active.sum())
+        assert np.array_equal(u[~active], u0[~active])
+        assert np.array_equal(r[~active], r0[~active])
+        np.testing.assert_allclose(u, want_u, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(r, want_r, rtol=1e-13, atol=0)
+        assert np.array_equal(c, want_c)
+        # both decisions occur among the active blocks
+        ca = c[active]
+        assert 0 < np.count_nonzero(ca == 0) < ca.size
+
+
+def test_block_rule_of_1x1_blocks_is_the_pixel_rule(orc):
+    """Blocks of one pixel decide exactly as the per-pixel rule (Section 4)."""
+    thin = dict(mode="rel", tau=1e-3, hysteresis=2, reset_period=5, compact_period=5)
+    h = synth.disc(3)
+    f = synth.observe(synth.latent_image(30, 41, 12), h, "poisson", 12)
+    fd = f.astype(np.float64)
+    a = [fd.copy(), np.zeros_like(fd), np.zeros(f.shape, np.uint8)]
+    b = [fd.copy(), np.zeros_like(fd), np.zeros(f.shape, np.uint8)]
+    for k in range(23):
+        na = orc.thin_step(fd, a[0], a[1], a[2], h, k, thin)
+        nb = orc.thin_step_blocks(fd, b[0], b[1], b[2], h, k, thin, 1)
+        assert na == nb
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2])
+    assert 0 < np.count_nonzero(a[2] >= 2) < f.size
+
+
+def test_block_rule_tau_zero_is_plain_rl(orc):
+    h = synth.disc(2)
+    f = synth.observe(synth.latent_image(37, 29, 13), h, "poisson", 13)
+    thin = dict(mode="abs", tau=0.0, hysteresis=1, reset_period=10, compact_period=10,
+                block=8)
+    out = orc.rl_thin(f, h, 12, thin)
+    assert np.array_equal(out["u"], orc.rl(f, h, 12))
+    assert (out["active"] == f.size).all()
+
+
 def test_below_many_matches_below(orc):
     rng = np.random.default_rng(9)
     b = rng.uniform(0.0, 2.0, 400).astype(np.float32)
@@ -403,6 +497,15 @@ def _pins_pass(o):
                 np.array_equal(rr[~active], r0[~active]) and
                 np.allclose(uu, want_u, rtol=1e-13, atol=0)):
             return False
+        # block rule: a block counts up only when all of its pixels pass the test
+        tb = dict(mode="rel", tau=0.25, hysteresis=3, reset_period=10, compact_period=10,
+                  block=4)
+        f, u0, r0, c0, tc = _block_state((23, 30), 4, 3, 104)
+        _, _, want_c, _ = _block_step_expected(f, u0, r0, tc, 4, hd, tb, "reflect", False)
+        uu, rr, cc = u0.copy(), r0.copy(), c0.copy()
+        o.thin_step(f, uu, rr, cc, hd, 13, tb)
+        if not np.array_equal(cc, want_c):
+            return False
         e = 2.0 ** -13
         if o.below(1.0 + e, 1.0, "abs", e) or not o.below(1.0 + e, 1.0, "abs", 1.5 * e):
             return False
@@ -415,7 +518,7 @@ def _pins_pass(o):
 
 def test_planted_mistakes_are_caught():
     assert _pins_pass(oracle.Oracle(0))
-    for m in range(1, 12):
+    for m in range(1, 13):
         assert not _pins_pass(oracle.Oracle(m)), f"mutant {m} passed the pins"
 
 

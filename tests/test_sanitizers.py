@@ -102,6 +102,10 @@ def test_oracle_under_sanitizers(drivers, H, W, h, bc, mode):
     assert np.array_equal(got["thin_r"].reshape(H, W), th["r"])
     assert np.array_equal(got["thin_cnt"].reshape(H, W), th["cnt"].astype(np.float64))
     assert np.array_equal(got["thin_active"], th["active"].astype(np.float64))
+    tb = o.rl_thin(f, h, K, dict(thin, block=3), bc)
+    assert np.array_equal(got["block_u"].reshape(H, W), tb["u"])
+    assert np.array_equal(got["block_cnt"].reshape(H, W), tb["cnt"].astype(np.float64))
+    assert np.array_equal(got["block_active"], tb["active"].astype(np.float64))
     assert np.array_equal(got["tv"].reshape(H, W), o.rl_tv(f, h, K, 0.1, 1e-3, bc))
     assert np.array_equal(got["robust"].reshape(H, W), o.rl_robust(f, h, K, 0.05, bc))
     assert got["sum"][0] == o.sum(f64)
