@@ -524,13 +524,10 @@ def report_thinned(args, dev):
     job = synth.job_for_config(3)[0]
     f = torch.from_numpy(job["f"]).to(dev)
     K = job["iters"]
+    N = job["f"].size
     log(f"report 3: {job['f'].shape} disc r=16, K={K}, thin={job['thin']}")
-    res = {}
-    for name, thin in (("plain", None), ("thinned", job["thin"])):
-        j = Job(f, job["psf"], thin=thin)
-        j.iterate(2)
-        torch.cuda.synchronize()
-        j.close()
+
+    def run(thin):
         j = Job(f, job["psf"], thin=thin)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -539,46 +536,46 @@ def report_thinned(args, dev):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sched = j.thin_schedule() if thin else None
-        res[name] = dict(u=u.cpu().numpy(), t=dt, st=st, sched=sched, info=j.describe())
         j.close()
-        log(f"report 3: {name} {dt * 1e3:.1f} ms")
-    N = job["f"].size
-    sched = np.array(res["thinned"]["sched"], dtype=np.float64) / N
-    omitted = 1.0 - sched.mean()
-    # threshold sweep (as in Table 2): time, omitted fraction and PSNR against plain
-    sweep = []
-    for tau in (3e-4, 1e-3, 3e-3, 1e-2):
-        thin = dict(job["thin"], tau=tau)
-        j = Job(f, job["psf"], thin=thin)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        j.iterate(K)
-        u = j.result()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        sc = np.array(j.thin_schedule(), dtype=np.float64) / N
-        sweep.append(dict(tau=tau, ms=round(dt * 1e3, 2),
-                          speedup=round(res["plain"]["t"] / dt, 3),
-                          omitted_fraction=round(float(1.0 - sc.mean()), 4),
-                          psnr_vs_plain_db=round(_psnr(u.cpu().numpy(), res["plain"]["u"]), 2)))
-        j.close()
-        log(f"report 3: tau {tau}: {sweep[-1]}")
+        return dict(u=u.cpu().numpy(), t=dt, st=st, sched=sched)
+
+    run(None)  # warm-up
+    plain = run(None)
+    log(f"report 3: plain {plain['t'] * 1e3:.1f} ms")
+    # Section 4's per-pixel rule and the block rule (freeze decisions per block), at
+    # configuration 3's threshold and over a threshold sweep as in Table 2
+    rules = (("pixel", 0), ("block64", 64), ("block16", 16))
+    res = {}
+    for tau in (1e-4, 3e-4, 1e-3, 3e-3, 1e-2):
+        for rule, B in rules:
+            out = run(dict(job["thin"], tau=tau, block=B))
+            sc = np.array(out["sched"], dtype=np.float64) / N
+            psnr = _psnr(out["u"], plain["u"])
+            res[(rule, tau)] = dict(
+                rule=rule, tau=tau, ms=round(out["t"] * 1e3, 2),
+                speedup=round(plain["t"] / out["t"], 3),
+                omitted_fraction=round(float(1.0 - sc.mean()), 4),
+                # None: bit-identical to the unthinned run (nothing froze)
+                psnr_vs_plain_db=None if np.isinf(psnr) else round(psnr, 2),
+                flux=out["st"].flux)
+            if tau == 1e-4:
+                res[(rule, tau)]["active_fraction_at_k_5_15_25"] = [
+                    round(float(x), 4) for x in sc[5:30:10]]
+            log(f"report 3: {res[(rule, tau)]}")
+    main = res[("pixel", 1e-4)]
     return {
         "report": "thinned RL, config 3",
         "workload": "2048x2048, disc r=16, Poisson peak 1000, 500 iterations, rel tau 1e-4, H=5, R=10, C=10",
-        "plain_ms": res["plain"]["t"] * 1e3,
-        "thinned_ms": res["thinned"]["t"] * 1e3,
-        "speedup": res["plain"]["t"] / res["thinned"]["t"],
-        "logical_px_it_per_s_thinned": N * K / res["thinned"]["t"],
-        "active_px_it_per_s_thinned": float(sched.sum() * N) / res["thinned"]["t"],
-        "px_it_per_s_plain": N * K / res["plain"]["t"],
-        "omitted_fraction": float(omitted),
-        "psnr_thinned_vs_plain_db": _psnr(res["thinned"]["u"], res["plain"]["u"]),
-        "active_fraction_at_k_5_15_25": [round(float(x), 4) for x in sched[5::10]],
-        "active_fraction_last_10": [round(float(x), 4) for x in sched[-10:]],
-        "flux_plain": res["plain"]["st"].flux,
-        "flux_thinned": res["thinned"]["st"].flux,
-        "tau_sweep": sweep,
+        "plain_ms": plain["t"] * 1e3,
+        "px_it_per_s_plain": N * K / plain["t"],
+        "thinned_ms": main["ms"],
+        "speedup": main["speedup"],
+        "omitted_fraction": main["omitted_fraction"],
+        "psnr_thinned_vs_plain_db": main["psnr_vs_plain_db"],
+        "block64_ms": res[("block64", 1e-4)]["ms"],
+        "block64_speedup": res[("block64", 1e-4)]["speedup"],
+        "flux_plain": plain["st"].flux,
+        "rules_and_taus": [res[k] for k in sorted(res, key=lambda k: (k[1], k[0]))],
     }
 
 

@@ -108,6 +108,19 @@ typedef struct rl_thin {
     int32_t keep_list;      /* 1: also build the per-pixel active list at every rebuild
                                (exported by rl_active_list); 0: only the tile list that
                                distributes the work is built                              */
+    int32_t block;          /* 0 or 1: the per-pixel rule of Section 4 (eq. 4-5).  8, 16,
+                               32 or 64: the block rule, a refinement of Section 4's
+                               adaptive update rule: the image is cut into block x block
+                               squares aligned at (0, 0) (cut by the image edge), each with
+                               one counter; a block counts up when the test above holds for
+                               every one of its pixels and restarts at 0 otherwise, and
+                               every pixel of an active block is updated (frozen blocks
+                               keep u and r; active neighbours read their stale r).  The
+                               counters exchanged by rl_get_state / rl_set_state stay per
+                               pixel: every pixel carries its block's counter, and on input
+                               a block takes the counter of its top-left pixel.  The
+                               tiled kernels then run 64 x 64 tiles (strip 8); the other
+                               values give RL_E_INVAL                                     */
 } rl_thin;
 
 /* Kernel-shape and launch knobs (0 = let the library choose).  Results do not depend on

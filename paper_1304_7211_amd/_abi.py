@@ -41,7 +41,8 @@ RL_STATIC_SCRATCH_BYTES = 64 << 20
 class rl_thin(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float),
                 ("hysteresis", ctypes.c_int32), ("reset_period", ctypes.c_int32),
-                ("compact_period", ctypes.c_int32), ("keep_list", ctypes.c_int32)]
+                ("compact_period", ctypes.c_int32), ("keep_list", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
 
 class rl_tuning(ctypes.Structure):

@@ -32,7 +32,9 @@ static_assert(sizeof(DevSpan) == sizeof(rl::Span), "span layout");
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kLdsLimit = 160 * 1024;
+// dynamic LDS of one workgroup: 160 KB per CU less the phase kernels' static arrays (the
+// block rule's per-wavefront failure words, the persistent schedule's task slot)
+constexpr size_t kLdsLimit = 160 * 1024 - 256;
 constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
 constexpr size_t kSpanPad = 2;  // zero descriptors after each span table (read-ahead)
 
@@ -64,7 +66,7 @@ struct Config {
 struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, mf_conv, mf_corr, cnt, plist, tflag, tlist,
         bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, tvg, wt,
-        total;
+        cntb, total;
 };
 
 // counters block (int64 slots)
@@ -72,6 +74,18 @@ enum Ctr { C_PLIST_LEN = 0, C_TLIST_LEN, C_ACTIVE_TOTAL, C_F_INVALID, C_ACTIVE_N
            C_COUNT = 8 };
 
 int64_t thin_blocks(int64_t N) { return (N + 255) / 256; }
+
+// Block rule (thin.block >= 8): log2 of the block side, else 0 (per-pixel rule).
+int block_lg(const rl_params* p) {
+    if (p->thin.mode == RL_THIN_OFF || p->thin.block < 8) return 0;
+    int lg = 0;
+    while ((1 << lg) < p->thin.block) ++lg;
+    return lg;
+}
+int64_t block_cols(const rl_params* p, int lg) { return (p->width + (1 << lg) - 1) >> lg; }
+int64_t block_count(const rl_params* p, int lg) {
+    return block_cols(p, lg) * ((p->height + (1 << lg) - 1) >> lg);
+}
 
 bool is_full(int64_t k, int R) { return k == 0 || (R > 0 && k % R == 0); }
 bool is_rebuild(int64_t k, int R, int C) {
@@ -349,9 +363,11 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     // latency-bound kernels more wavefronts on small images
     // defaults from measurements with 8 wavefronts per workgroup on 64^2 .. 2048^2 images:
     // 4 outputs per lane below 0.5 Mpx, 8 from there on
-    const int def_S = npx >= ((int64_t)1 << 19) ? 8 : 4;
-    const int span_S = p->tuning.strip ? p->tuning.strip : def_S;
-    const int slide_S = p->tuning.strip ? p->tuning.strip : def_S;
+    // the block rule takes its decisions per block inside 64 x 64 tiles: strips of 8
+    const bool blk = block_lg(p) > 0;
+    const int def_S = blk ? 8 : npx >= ((int64_t)1 << 19) ? 8 : 4;
+    const int span_S = blk ? 8 : p->tuning.strip ? p->tuning.strip : def_S;
+    const int slide_S = blk ? 8 : p->tuning.strip ? p->tuning.strip : def_S;
     if (span_S != 4 && span_S != 8 && span_S != 16 && span_S != 32) { *why = "tuning.strip"; return RL_E_INVAL; }
     const bool mfma_sched = sched == RL_SCHED_AUTO || sched == RL_SCHED_TWO_PASS;
     if (path == RL_PATH_MFMA) {
@@ -483,6 +499,10 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
                      : 64 + t.lane_max - t.lane_min;
         if (nx > 64 * rlk::MAXC) { *why = "PSF extent too wide for the tile loader"; return RL_E_UNSUPPORTED; }
     }
+    if (blk && (cfg->TA != 64 || cfg->TB != 64)) {
+        *why = "the block rule needs 64 x 64 tiles";
+        return RL_E_UNSUPPORTED;
+    }
     const int la = cfg->orient == rlk::ORIENT_ROWS ? H : W;  // lane axis length
     const int lb = cfg->orient == rlk::ORIENT_ROWS ? W : H;
     cfg->tiles_a = (la + cfg->TA - 1) / cfg->TA;
@@ -534,6 +554,8 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
         L.boffs = take(thin_blocks(N) * 4);
         L.sched = take(rlk::SCHED_RING * 8);
         L.act = take(2 * rlk::ACT_SLOTS * 4);
+        const int lg = block_lg(p);
+        L.cntb = lg ? take((size_t)block_count(p, lg)) : 0;  // block rule: one counter per block
     }
     L.ctr = take(C_COUNT * 8);
     L.args = take(2 * sizeof(PhaseArgs));
@@ -564,6 +586,11 @@ rl_status validate_params(const rl_params* p, std::string* why) {
         if (!(p->thin.tau >= 0.f) || std::isinf(p->thin.tau)) { *why = "tau"; return RL_E_INVAL; }
         if (p->thin.hysteresis < 1 || p->thin.hysteresis > 255) { *why = "hysteresis in [1, 255]"; return RL_E_INVAL; }
         if (p->thin.reset_period < 0 || p->thin.compact_period < 0) { *why = "periods"; return RL_E_INVAL; }
+        const int b = p->thin.block;
+        if (!(b == 0 || b == 1 || b == 8 || b == 16 || b == 32 || b == 64)) {
+            *why = "thin.block must be 0, 1, 8, 16, 32 or 64";
+            return RL_E_INVAL;
+        }
     }
     return RL_OK;
 }
@@ -850,7 +877,11 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
             }
     }
     if (j->p.thin.mode != RL_THIN_OFF) {
-        a.cnt = j->at<uint8_t>(j->L.cnt);
+        const int lg = block_lg(&j->p);
+        a.cnt = lg ? j->at<uint8_t>(j->L.cntb) : j->at<uint8_t>(j->L.cnt);
+        a.blk_lg = lg;
+        a.blk_w = lg ? (int32_t)block_cols(&j->p, lg) : 0;
+        a.tflag = lg ? j->at<int32_t>(j->L.tflag) : nullptr;
         a.thin_mode = j->p.thin.mode;
         a.hyst = j->p.thin.hysteresis;
         a.reset_period = j->p.thin.reset_period;
@@ -862,6 +893,14 @@ PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
         a.tile_count = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
     }
     return a;
+}
+
+// Block rule: write every pixel's counter (its block's) to dst (N bytes, device).
+rl_status expand_blocks(rl_job* j, uint8_t* dst, hipStream_t s) {
+    const int lg = block_lg(&j->p);
+    return dev_err(launch("block_expand", rlk::block_expand_kernel, dim3(grid_for(j->N)), dim3(256), 0, s,
+                          (const uint8_t*)j->at<uint8_t>(j->L.cntb), dst, j->N, j->W, lg,
+                          (int)block_cols(&j->p, lg)), "block expand");
 }
 
 rl_status rebuild_lists(rl_job* j, hipStream_t s) {
@@ -882,16 +921,27 @@ rl_status rebuild_lists(rl_job* j, hipStream_t s) {
     const int nb = (int)thin_blocks(j->N);
     a.n_blocks = nb;
     rl_status st;
-    if ((st = dev_err(launch("thin_count", rlk::thin_count_kernel, dim3(nb), dim3(256), 0, s, a), "thin_count"))) return st;
+    int ntiles = j->cfg.tiles_a * j->cfg.tiles_b;
+    const bool blk = block_lg(&j->p) > 0;
+    if (blk) {
+        // block rule: the phase-B kernels keep every tile's flag up to date, so the list is
+        // compacted straight from the flags; the per-pixel list is built only when kept
+        // (from the expanded counters; thin_count then sets flags that are already set)
+        if (j->p.thin.keep_list) {
+            if ((st = expand_blocks(j, j->at<uint8_t>(j->L.cnt), s))) return st;
+            if ((st = dev_err(launch("thin_count", rlk::thin_count_kernel, dim3(nb), dim3(256), 0, s, a), "thin_count"))) return st;
+        }
+    } else if ((st = dev_err(launch("thin_count", rlk::thin_count_kernel, dim3(nb), dim3(256), 0, s, a), "thin_count"))) {
+        return st;
+    }
     if (j->p.thin.keep_list) {
         if ((st = dev_err(launch("thin_scan", rlk::scan_counts_kernel, dim3(1), dim3(1024), 0, s,
                                  (const int32_t*)a.block_counts, a.block_offsets, nb, a.plist_len), "thin_scan"))) return st;
         if ((st = dev_err(launch("thin_scatter", rlk::thin_scatter_kernel, dim3(nb), dim3(256), 0, s, a), "thin_scatter"))) return st;
     }
-    int ntiles = j->cfg.tiles_a * j->cfg.tiles_b;
     int64_t* tcount = j->at<int64_t>(j->L.ctr) + C_TLIST_LEN;
     if ((st = dev_err(launch("tile_compact", rlk::tile_compact_kernel, dim3(1), dim3(1024), 0, s,
-                             a.tflag, ntiles, j->at<int32_t>(j->L.tlist), tcount), "tile_compact"))) return st;
+                             a.tflag, ntiles, j->at<int32_t>(j->L.tlist), tcount, blk ? 0 : 1), "tile_compact"))) return st;
     j->list_valid = true;
     // Read the active-tile count back without waiting: a later iteration uses it (once the
     // copy has landed) to skip the tile list when nearly every tile is active.
@@ -1105,7 +1155,10 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
             if (st) return st;
         }
         la.kb = lb.kb = j->k;
-        if (thin) la.one.list_ok = lb.one.list_ok = use_tile_list(j) ? 1 : 0;
+        if (thin) {
+            la.one.list_ok = lb.one.list_ok = use_tile_list(j) ? 1 : 0;
+            la.one.full = lb.one.full = is_full(j->k, j->p.thin.reset_period) ? 1 : 0;
+        }
         if (rl_status tst = enqueue_tv(j, s)) return tst;
         rl_status st = dev_err(launch(na, fa, dim3(ntiles), dim3(c.threads), c.lds_a, s, la), na);
         if (st) return st;
@@ -1403,7 +1456,14 @@ rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, 
     if (p->thin.mode != RL_THIN_OFF) {
         int64_t nt = (int64_t)j->cfg.tiles_a * j->cfg.tiles_b;
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(N / 4 + 1)), dim3(256), 0, s, j->at<uint32_t>(j->L.cnt), 0u, (N + 3) / 4), "zero cnt"))) { delete j; return st; }
-        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(nt)), dim3(256), 0, s, j->at<uint32_t>(j->L.tflag), 0u, nt), "zero tflag"))) { delete j; return st; }
+        const int lg = block_lg(p);
+        if (lg) {
+            const int64_t nbk = block_count(p, lg);
+            if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(nbk / 4 + 1)), dim3(256), 0, s, j->at<uint32_t>(j->L.cntb), 0u, (nbk + 3) / 4), "zero block cnt"))) { delete j; return st; }
+        }
+        // tile flags: scratch of the list rebuild (0), or under the block rule every tile
+        // active (1, all counters start at 0)
+        if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(nt)), dim3(256), 0, s, j->at<uint32_t>(j->L.tflag), lg ? 1u : 0u, nt), "init tflag"))) { delete j; return st; }
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(rlk::SCHED_RING * 2)), dim3(256), 0, s, j->at<uint32_t>(j->L.sched), 0u, (int64_t)rlk::SCHED_RING * 2), "zero ring"))) { delete j; return st; }
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(2), dim3(256), 0, s, j->at<uint32_t>(j->L.act), 0u, (int64_t)2 * rlk::ACT_SLOTS), "zero act"))) { delete j; return st; }
     }
@@ -1453,6 +1513,7 @@ rl_status rl_result(rl_job* j, float* u_out, rl_stats* st) {
     if (thin && (rs = finalize_thin(j, s))) return rs;
     if ((rs = dev_err(launch("reduce_sum", rlk::reduce_sum_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
                              (const float*)j->cur_u(), j->N, j->at<double>(j->L.red)), "reduce"))) return rs;
+    if (thin && block_lg(&j->p) && (rs = expand_blocks(j, j->at<uint8_t>(j->L.cnt), s))) return rs;
     if (thin) {
         if ((rs = dev_err(launch("count_active", rlk::count_active_kernel, dim3(rlk::RED_BLOCKS), dim3(256), 0, s,
                                  (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N, (int)j->p.thin.hysteresis, j->at<int64_t>(j->L.red_i)), "count"))) return rs;
@@ -1760,7 +1821,10 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
                 if (m == 1) {
                     rl_job* j1 = jobs[g.idx[0]];
                     la.one = phase_args(j1, phase == 1, j1->k);
-                    if (j1->p.thin.mode != RL_THIN_OFF) la.one.list_ok = use_tile_list(j1) ? 1 : 0;
+                    if (j1->p.thin.mode != RL_THIN_OFF) {
+                        la.one.list_ok = use_tile_list(j1) ? 1 : 0;
+                        la.one.full = is_full(j1->k + kb, j1->p.thin.reset_period) ? 1 : 0;
+                    }
                 }
                 st = dev_err(launch(phase ? g.nb : g.na, phase ? g.fb : g.fa, dim3(g.prefix[m]),
                                     dim3(g.threads), phase ? g.lds_b : g.lds_a, gsm, la),
@@ -1791,7 +1855,11 @@ rl_status rl_get_state(rl_job* j, float* u, float* r, uint8_t* cnt, int64_t* k_o
     if (r && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, r, (const float*)j->at<float>(j->L.r), j->N), "get r"))) return st;
     if (cnt) {
         if (j->p.thin.mode == RL_THIN_OFF) return RL_E_STATE;
-        if ((st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, cnt, (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N), "get cnt"))) return st;
+        if (block_lg(&j->p)) {
+            if ((st = expand_blocks(j, cnt, s))) return st;
+        } else if ((st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, cnt, (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->N), "get cnt"))) {
+            return st;
+        }
     }
     if (k_out) *k_out = j->k;
     return j->persist_used ? check_persist_abort(j, s) : RL_OK;
@@ -1809,6 +1877,20 @@ rl_status rl_set_state(rl_job* j, const float* u, const float* r, const uint8_t*
     if (u && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->cur_u(), u, j->N), "set u"))) return st;
     if (r && (st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.r), r, j->N), "set r"))) return st;
     if (cnt && (st = dev_err(launch("copy_u8", rlk::copy_u8_kernel, dim3(g), dim3(256), 0, s, j->at<uint8_t>(j->L.cnt), cnt, j->N), "set cnt"))) return st;
+    if (cnt) {
+        if (const int lg = block_lg(&j->p)) {
+            // block rule: each block takes the counter of its top-left pixel
+            const int64_t nbk = block_count(&j->p, lg);
+            if ((st = dev_err(launch("block_compress", rlk::block_compress_kernel, dim3(grid_for(nbk)), dim3(256), 0, s,
+                                     (const uint8_t*)j->at<uint8_t>(j->L.cnt), j->at<uint8_t>(j->L.cntb), j->W, lg,
+                                     (int)block_cols(&j->p, lg), nbk), "set block cnt"))) return st;
+            const int ntiles = j->cfg.tiles_a * j->cfg.tiles_b;
+            if ((st = dev_err(launch("block_tiles", rlk::block_tiles_kernel, dim3((ntiles + 255) / 256), dim3(256), 0, s,
+                                     (const uint8_t*)j->at<uint8_t>(j->L.cntb), j->H, j->W, lg,
+                                     (int)block_cols(&j->p, lg), (int)j->p.thin.hysteresis, j->cfg.orient,
+                                     j->cfg.tiles_a, ntiles, j->at<int32_t>(j->L.tflag)), "set tile flags"))) return st;
+        }
+    }
     j->k = k;
     j->list_valid = false;
     if (j->p.thin.mode != RL_THIN_OFF) {

@@ -94,14 +94,14 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-// The float32 convergence test of thinned RL (Section 4), one rounded op per step.
+// The float32 convergence test of thinned RL (Section 4), one rounded op per step: false
+// for tau <= 0; else true when a and b are both 0 or |a - b| < t (t = tau, or tau * b for
+// the relative test).  Written without branches (bitwise and / or of the comparisons), so
+// that a wavefront evaluates it without exec-mask bookkeeping.
 __device__ __forceinline__ bool thin_below(float a, float b, int mode, float tau) {
-    if (!(tau > 0.f)) return false;
-    if (b == 0.f && a == 0.f) return true;
-    float d = __fsub_rn(a, b);
-    float ad = fabsf(d);
-    float t = (mode == THIN_REL) ? __fmul_rn(tau, b) : tau;
-    return ad < t;
+    const float t = (mode == THIN_REL) ? __fmul_rn(tau, b) : tau;
+    const bool zero = (a == 0.f) & (b == 0.f);
+    return (tau > 0.f) & (zero | (fabsf(__fsub_rn(a, b)) < t));
 }
 
 // r = f / v for v > 0, else 0 (IEEE-rounded division).
@@ -117,7 +117,8 @@ struct PhaseArgs {
     const float* f;       // phase A
     float* r;             // phase A output
     float* u;             // phase B in/out
-    uint8_t* cnt;         // thinning counters (NULL when off)
+    uint8_t* cnt;         // thinning counters (NULL when off): one per pixel, or one per
+                          // block under the block rule (blk_lg > 0)
     const DevSpan* spans; // operator table
     const float* wts;     // operator weights (padded with zeros)
     int32_t n_spans;
@@ -136,6 +137,9 @@ struct PhaseArgs {
     const float* tvg;              // phase B: TV denominator 1 - lambda div(...) or NULL
     int32_t wit;                   // sliding kernel: a span at least one strip long, or -1
     float* store;                  // robust variant: store the window sum here and nothing else
+    int32_t blk_lg;                // block rule: log2 of the block side (3..6), 0 = per pixel
+    int32_t blk_w;                 // block rule: blocks per image row
+    int32_t* tflag;                // block rule: per tile, 1 while it holds an active block
 };
 
 // One launch covers the tiles of n_jobs jobs: job j owns workgroups
@@ -165,6 +169,9 @@ __device__ __forceinline__ PhaseArgs load_args(ConstArgsPtr t) {
     p.tvg = t->tvg;
     p.wit = t->wit;
     p.store = t->store;
+    p.blk_lg = t->blk_lg;
+    p.blk_w = t->blk_w;
+    p.tflag = t->tflag;
     return p;
 }
 
@@ -209,7 +216,9 @@ __device__ __forceinline__ void thin_finalize_wave(int32_t* act_part, int64_t* s
 // Thinned mode: iteration k is full when k == 0 or k % R == 0; on other steps the tiles
 // come from the compacted list.  The first wavefront of a job's first workgroup in phase A
 // folds the active count of iteration k - 1 into the schedule ring (phase B of iteration
-// k - 1 spread it over ACT_SLOTS counters, see add_active).
+// k - 1 spread it over ACT_SLOTS counters, one atomic add per tile in thin_finish: spread,
+// so that thousands of tiles do not serialise on one address; integer adds, so the total
+// does not depend on their order).
 template <bool PHASE_B>
 __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int TA, int TB,
                                         int& a0, int& b0) {
@@ -232,7 +241,9 @@ __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int T
     p.k += L.kb;
     bool use_list = false;
     if (p.cnt) {
-        p.full = (p.k == 0 || (p.reset_period > 0 && p.k % p.reset_period == 0)) ? 1 : 0;
+        // single-job launches carry the host's full-step flag; batch launches derive it
+        if (L.n_jobs != 1)
+            p.full = (p.k == 0 || (p.reset_period > 0 && p.k % p.reset_period == 0)) ? 1 : 0;
         use_list = !p.full && p.list_ok;
         if (!PHASE_B && local == 0 && threadIdx.x < 64)
             thin_finalize_wave(p.act_part, p.sched, p.active_total, p.k - 1, p.k);
@@ -249,6 +260,11 @@ __device__ __forceinline__ bool resolve(const LaunchArgs& L, PhaseArgs& p, int T
     if (local >= n) return false;
     const int slot = (L.n_jobs == 1) ? xcd_tile(local, n) : local;
     const int t = use_list ? ((ConstIntPtr)p.tile_list)[slot] : slot;
+    // block rule, non-full step: a tile whose blocks have all frozen (since the list was
+    // built, or since the last rebuild found nearly every tile active and dropped the list)
+    // has nothing to do; its flag was written by the tile's own phase B of the previous
+    // iteration
+    if (p.cnt && p.blk_lg && !p.full && ((ConstIntPtr)p.tflag)[t] == 0) return false;
     a0 = (t % p.tiles_a) * TA;
     b0 = (t / p.tiles_a) * TB;
     return true;
@@ -332,27 +348,43 @@ __device__ __forceinline__ bool tile_zeros(const int* zf) {
     return __builtin_amdgcn_readfirstlane(o) != 0;
 }
 
-// Epilogue inputs of one output at linear position q: f (phase A) or u^k (phase B), and
-// the convergence counter in thinned mode.  Gathered for all outputs of a lane before any
-// is applied, so the global loads overlap.
+// Epilogue inputs of one output at pixel (y, x), linear position q: f (phase A) or u^k
+// (phase B), and the convergence counter in thinned mode (the pixel's own, or its block's
+// under the block rule).  Gathered for all outputs of a lane before any is applied, so the
+// global loads overlap.
 struct EpiIn {
     float x;
     uint8_t c8;
 };
 
+// Index of the counter that decides pixel (y, x): q itself, or its block's under the block
+// rule (blocks of 2^blk_lg pixels a side, aligned at (0, 0)).
+__device__ __forceinline__ size_t cnt_idx(const PhaseArgs& p, int y, int x, size_t q) {
+    return p.blk_lg ? (size_t)(y >> p.blk_lg) * p.blk_w + (x >> p.blk_lg) : q;
+}
+
+// Block rule: bit of pixel (y, x)'s block among the blocks of its 64 x 64 tile (tiles are
+// 64-aligned, so the tile-relative position is the low six bits of y and x).
+__device__ __forceinline__ int blk_bit(const PhaseArgs& p, int y, int x) {
+    return (((y & 63) >> p.blk_lg) << (6 - p.blk_lg)) | ((x & 63) >> p.blk_lg);
+}
+
 template <bool PHASE_B>
-__device__ __forceinline__ EpiIn epi_load(const PhaseArgs& p, size_t q) {
+__device__ __forceinline__ EpiIn epi_load(const PhaseArgs& p, int y, int x, size_t q) {
     EpiIn e;
     e.x = PHASE_B ? p.u[q] : p.f[q];
-    e.c8 = p.cnt ? p.cnt[q] : (uint8_t)0;
+    e.c8 = p.cnt ? p.cnt[cnt_idx(p, y, x, q)] : (uint8_t)0;
     return e;
 }
 
 // Apply the epilogue: phase A writes r = f / v; phase B writes u^{k+1} = u^k . c and, in
-// thinned mode, the counter.  Inactive pixels (thinned, non-full step) are left alone.
-// Returns 1 if the pixel was active.
+// thinned mode, the counter (per-pixel rule) or, under the block rule, sets the pixel's
+// block bit in fails when the pixel fails the convergence test (block_finish turns the bits
+// into block counters).  Inactive pixels (thinned, non-full step) are left alone.  Returns
+// 1 if the pixel was active.
 template <bool PHASE_B>
-__device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, float val) {
+__device__ __forceinline__ int epi_apply(const PhaseArgs& p, int y, int x, size_t q, EpiIn e,
+                                         float val, uint64_t& fails) {
     if (p.cnt && !(p.full || (int)e.c8 < p.hyst)) return 0;
     if (p.store) {  // robust variant: the plain convolution or correlation
         p.store[q] = val;
@@ -368,21 +400,117 @@ __device__ __forceinline__ int epi_apply(const PhaseArgs& p, size_t q, EpiIn e, 
         p.u[q] = un;
         if (p.cnt && p.thin_mode != THIN_OFF) {
             bool below = thin_below(un, e.x, p.thin_mode, p.tau);
-            p.cnt[q] = below ? (uint8_t)(e.c8 < 255 ? e.c8 + 1 : 255) : (uint8_t)0;
+            if (p.blk_lg) {
+                fails |= (uint64_t)(!below) << blk_bit(p, y, x);
+            } else {
+                p.cnt[q] = below ? (uint8_t)(e.c8 < 255 ? e.c8 + 1 : 255) : (uint8_t)0;
+            }
         }
     }
     return 1;
 }
 
-// One atomic add per wavefront of its active-pixel count (thinned mode), into one of
-// ACT_SLOTS counters of bank k & 1 (spread, so thousands of wavefronts do not serialise on
-// one address); integer adds, so the total does not depend on their order.  wave_total is
-// wavefront-uniform (summed from ballots).
-__device__ __forceinline__ void add_active(const PhaseArgs& p, int wave_total) {
-    if (!p.cnt) return;
-    if ((threadIdx.x & 63) == 0 && wave_total) {
-        const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave_id()) % ACT_SLOTS);
-        atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + slot], wave_total);
+// Block rule, phase B: the counter of block threadIdx.x of the 64 x 64 tile at (ty0, tx0)
+// (row, column of its top-left pixel), loaded with the epilogue inputs so that block_finish
+// needs no load of its own; 0 for threads without a block.
+template <bool PHASE_B>
+__device__ __forceinline__ uint8_t blk_own_load(const PhaseArgs& p, int ty0, int tx0) {
+    if (!PHASE_B || !p.cnt || !p.blk_lg) return 0;
+    const int per = 64 >> p.blk_lg, t = threadIdx.x;
+    if (t >= per * per) return 0;
+    const int by = (ty0 >> p.blk_lg) + t / per, bx = (tx0 >> p.blk_lg) + t % per;
+    if ((by << p.blk_lg) >= p.H || (bx << p.blk_lg) >= p.W) return 0;
+    return p.cnt[(size_t)by * p.blk_w + bx];
+}
+
+// OR and sum over the 64 lanes of a wavefront with DPP row shifts and row broadcasts
+// (gfx9 lane movement, a few cycles per step): prefix within each row of 16 lanes, then
+// across rows; lane 63 holds the result, which is returned to every lane.  Lanes whose
+// source falls outside the row contribute 0, the identity of both operations.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Block rule, end of phase B of one 64 x 64 tile (tile id `tile`, top-left pixel
+// (ty0, tx0)): the failure bits of every lane are OR-ed over the workgroup, then each
+// active block of the tile (one thread per block, own_c its counter) counts up if none of
+// its pixels failed the test, else restarts at 0.  Blocks cut by the image edge hold only
+// their pixels inside the image.  The tile's flag then records whether any of its blocks
+// is active in the next iteration, and the pixels of the tile's active blocks go into the
+// active count (one atomic add per tile).  Every thread of the workgroup must call it (it
+// synchronises).
+__device__ __forceinline__ void block_finish(const PhaseArgs& p, uint64_t fails, int ty0,
+                                             int tx0, uint8_t own_c, int tile) {
+    __shared__ uint64_t slot[16];
+    const uint32_t lo = wave_or((uint32_t)fails), hi = wave_or((uint32_t)(fails >> 32));
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (lane == 0) slot[wave_id()] = ((uint64_t)hi << 32) | lo;
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int lg = p.blk_lg, per = 64 >> lg;  // blocks per tile side
+    const int t = threadIdx.x;
+    bool next_active = false;
+    int area = 0;
+    if (t < per * per) {
+        const int by = (ty0 >> lg) + t / per, bx = (tx0 >> lg) + t % per;
+        const int y0 = by << lg, x0 = bx << lg;
+        if (y0 < p.H && x0 < p.W) {
+            uint64_t all = 0;
+            for (int w = 0; w < nw; ++w) all |= slot[w];
+            int c = own_c;
+            if (p.full || c < p.hyst) {
+                area = min(1 << lg, p.H - y0) * min(1 << lg, p.W - x0);
+                c = ((all >> t) & 1ull) ? 0 : (c < 255 ? c + 1 : 255);
+                p.cnt[(size_t)by * p.blk_w + bx] = (uint8_t)c;
+            }
+            next_active = c < p.hyst;
+        }
+    }
+    const bool any = __ballot(next_active) != 0ull;
+    const int n_active = wave_sum(area);
+    if (t == 0) {
+        p.tflag[tile] = any ? 1 : 0;
+        if (n_active)
+            atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + (int)(blockIdx.x % ACT_SLOTS)], n_active);
+    }
+}
+
+// End of a phase launch's tile in thinned mode: the active count and, in phase B under the
+// block rule, the block counters and the tile's flag.  a0, b0 are the tile origin along the
+// lane and strip axes (64 x 64 tiles under the block rule).  Called by every thread of the
+// workgroup.
+template <bool PHASE_B>
+__device__ __forceinline__ void thin_finish(const PhaseArgs& p, int n_active, uint64_t fails,
+                                            int ty0, int tx0, uint8_t own_c, int a0, int b0) {
+    if (!PHASE_B || !p.cnt) return;
+    if (p.blk_lg) {  // the active count comes from the block areas
+        block_finish(p, fails, ty0, tx0, own_c, (b0 >> 6) * p.tiles_a + (a0 >> 6));
+    } else {
+        // per-pixel rule: the wavefronts' counts summed in LDS, one atomic add per tile
+        __shared__ int wsum[16];
+        if ((threadIdx.x & 63) == 0) wsum[wave_id()] = n_active;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+            if (tot) atomicAdd(&p.act_part[(p.k & 1) * ACT_SLOTS + (int)(blockIdx.x % ACT_SLOTS)], tot);
+        }
     }
 }
 
@@ -434,11 +562,13 @@ __device__ __forceinline__ TileGeom<ORIENT> make_geom(const PhaseArgs& p, int a0
 // (lanes are consecutive columns, so every access is coalesced), for ORIENT_ROWS the
 // elements the lane handles after the LDS transpose.  Loaded at kernel entry so that they
 // travel together with the tile.
-// Plain jobs on images whose width is a multiple of 4: the ROWS epilogue moves four
-// consecutive outputs per lane with 16-byte loads and stores.  (Thinned, TV and robust jobs
-// keep the per-output epilogue: a general four-wide one measured slower for every job.)
+// Plain jobs on images whose width is a multiple of 4, and thinned jobs under the block
+// rule on such images: the ROWS epilogue moves four consecutive outputs per lane with
+// 16-byte loads and stores (the four share one block, so one counter decides them).  (Jobs
+// with per-pixel counters, TV and robust jobs keep the per-output epilogue: a general
+// four-wide one measured slower for every job.)
 __device__ __forceinline__ bool epi_vec(const PhaseArgs& p) {
-    return (p.W & 3) == 0 && !p.cnt && !p.tvg && !p.store;
+    return (p.W & 3) == 0 && (!p.cnt || p.blk_lg) && !p.tvg && !p.store;
 }
 
 template <int ORIENT, int S, int NW>
@@ -446,6 +576,7 @@ struct EpiPlan {
     static constexpr int TB = NW * S;
     static constexpr int PER = ORIENT == ORIENT_COLS ? S : (64 * TB) / (NW * 64);
     EpiIn in[PER];
+    uint8_t own_c;  // block rule, phase B: see blk_own_load
 };
 
 template <int ORIENT, int S, int NW>
@@ -466,6 +597,8 @@ __device__ __forceinline__ void epi_pos(int i, int a0, int b0, int& y, int& x) {
 template <int ORIENT, int S, int NW, bool PHASE_B>
 __device__ __forceinline__ void epi_prefetch(const PhaseArgs& p, int a0, int b0,
                                              EpiPlan<ORIENT, S, NW>& plan) {
+    plan.own_c = blk_own_load<PHASE_B>(p, ORIENT == ORIENT_COLS ? b0 : a0,
+                                       ORIENT == ORIENT_COLS ? a0 : b0);
     if (ORIENT == ORIENT_ROWS && S % 4 == 0 && epi_vec(p)) {
         constexpr int TB = NW * S;
 #pragma unroll
@@ -473,12 +606,13 @@ __device__ __forceinline__ void epi_prefetch(const PhaseArgs& p, int a0, int b0,
             const int flat = 4 * ((int)threadIdx.x + j * NW * 64);
             const int y = a0 + flat / TB, x = b0 + flat % TB;
             if (y < p.H && x < p.W) {
-                const float4 v = *reinterpret_cast<const float4*>(
-                    (PHASE_B ? p.u : p.f) + (size_t)y * p.W + x);
+                const size_t q = (size_t)y * p.W + x;
+                const float4 v = *reinterpret_cast<const float4*>((PHASE_B ? p.u : p.f) + q);
                 plan.in[4 * j].x = v.x;
                 plan.in[4 * j + 1].x = v.y;
                 plan.in[4 * j + 2].x = v.z;
                 plan.in[4 * j + 3].x = v.w;
+                plan.in[4 * j].c8 = p.cnt ? p.cnt[cnt_idx(p, y, x, q)] : (uint8_t)0;
             }
         }
         return;
@@ -487,7 +621,7 @@ __device__ __forceinline__ void epi_prefetch(const PhaseArgs& p, int a0, int b0,
     for (int i = 0; i < EpiPlan<ORIENT, S, NW>::PER; ++i) {
         int y, x;
         epi_pos<ORIENT, S, NW>(i, a0, b0, y, x);
-        if (x < p.W && y < p.H) plan.in[i] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+        if (x < p.W && y < p.H) plan.in[i] = epi_load<PHASE_B>(p, y, x, (size_t)y * p.W + x);
     }
 }
 
@@ -496,7 +630,9 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
                                               const float (&out)[S],
                                               const EpiPlan<ORIENT, S, NW>& plan) {
     const int lane = threadIdx.x & 63, wv = wave_id();
-    int n_active = 0;  // wavefront total, summed from ballots (phase B, thinned)
+    int n_active = 0;    // wavefront total, summed from ballots (phase B, thinned)
+    uint64_t fails = 0;  // block rule: blocks of this lane's pixels that failed the test
+    const int ty0 = ORIENT == ORIENT_COLS ? b0 : a0, tx0 = ORIENT == ORIENT_COLS ? a0 : b0;
     if (ORIENT == ORIENT_COLS) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -504,8 +640,8 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
             epi_pos<ORIENT, S, NW>(s, a0, b0, y, x);
             int act = 0;
             if (x < p.W && y < p.H)
-                act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[s], out[s]);
-            if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+                act = epi_apply<PHASE_B>(p, y, x, (size_t)y * p.W + x, plan.in[s], out[s], fails);
+            if (PHASE_B && p.cnt && !p.blk_lg) n_active += __popcll(__ballot(act));
         }
     } else {
         constexpr int TB = NW * S;
@@ -520,22 +656,34 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
                 const int flat = 4 * ((int)threadIdx.x + j * NW * 64);
                 const int row = flat / TB, col = flat % TB;
                 const int y = a0 + row, x = b0 + col;
+                bool act = false;
                 if (y < p.H && x < p.W) {
                     const float* st = lds + row * SP + col;
                     const EpiIn* e = &plan.in[4 * j];
+                    // block rule: the four outputs share one block and its counter
+                    act = !p.cnt || p.full || (int)e[0].c8 < p.hyst;
                     float4 o;
-                    if (!PHASE_B) {
+                    if (act && !PHASE_B) {
                         o = make_float4(rl_ratio(e[0].x, st[0]), rl_ratio(e[1].x, st[1]),
                                         rl_ratio(e[2].x, st[2]), rl_ratio(e[3].x, st[3]));
                         *reinterpret_cast<float4*>(p.r + (size_t)y * p.W + x) = o;
-                    } else {
+                    } else if (act) {
                         o = make_float4(__fmul_rn(e[0].x, st[0]), __fmul_rn(e[1].x, st[1]),
                                         __fmul_rn(e[2].x, st[2]), __fmul_rn(e[3].x, st[3]));
                         *reinterpret_cast<float4*>(p.u + (size_t)y * p.W + x) = o;
+                        if (p.cnt) {
+                            const bool all = thin_below(o.x, e[0].x, p.thin_mode, p.tau) &
+                                             thin_below(o.y, e[1].x, p.thin_mode, p.tau) &
+                                             thin_below(o.z, e[2].x, p.thin_mode, p.tau) &
+                                             thin_below(o.w, e[3].x, p.thin_mode, p.tau);
+                            fails |= (uint64_t)(!all) << blk_bit(p, y, x);
+                        }
                     }
                 }
+                if (PHASE_B && p.cnt && !p.blk_lg) n_active += 4 * __popcll(__ballot(act));
             }
-            return;  // plain jobs: no active count
+            thin_finish<PHASE_B>(p, n_active, fails, ty0, tx0, plan.own_c, a0, b0);
+            return;
         }
 #pragma unroll
         for (int i = 0; i < EpiPlan<ORIENT, S, NW>::PER; ++i) {
@@ -545,11 +693,12 @@ __device__ __forceinline__ void write_outputs(const PhaseArgs& p, float* lds, in
             epi_pos<ORIENT, S, NW>(i, a0, b0, y, x);
             int act = 0;
             if (y < p.H && x < p.W)
-                act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, plan.in[i], lds[row * SP + col]);
-            if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+                act = epi_apply<PHASE_B>(p, y, x, (size_t)y * p.W + x, plan.in[i],
+                                         lds[row * SP + col], fails);
+            if (PHASE_B && p.cnt && !p.blk_lg) n_active += __popcll(__ballot(act));
         }
     }
-    if (PHASE_B) add_active(p, n_active);
+    thin_finish<PHASE_B>(p, n_active, fails, ty0, tx0, plan.own_c, a0, b0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -727,8 +876,10 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int y = a0 + 16 * wv + 4 * q + t, x = b0 + 16 * bx + m;
-            if (y < p.H && x < p.W) ein[bx][t] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+            if (y < p.H && x < p.W) ein[bx][t] = epi_load<PHASE_B>(p, y, x, (size_t)y * p.W + x);
         }
+
+    const uint8_t own_c = blk_own_load<PHASE_B>(p, a0, b0);
 
     // source tile: float32 into LDS by DMA (load_tile: every row chunk in flight at once,
     // boundary fold applied to the addresses), then converted in LDS into the three bfloat16
@@ -787,6 +938,7 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     }
 
     int n_active = 0;
+    uint64_t fails = 0;
 #pragma unroll
     for (int bx = 0; bx < 4; ++bx)
 #pragma unroll
@@ -794,10 +946,11 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
             const int y = a0 + 16 * wv + 4 * q + t, x = b0 + 16 * bx + m;
             const float v = (even[bx][t] + odd[bx][t]) + small[bx][t];
             int act = 0;
-            if (y < p.H && x < p.W) act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, ein[bx][t], v);
-            if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+            if (y < p.H && x < p.W)
+                act = epi_apply<PHASE_B>(p, y, x, (size_t)y * p.W + x, ein[bx][t], v, fails);
+            if (PHASE_B && p.cnt && !p.blk_lg) n_active += __popcll(__ballot(act));
         }
-    if (PHASE_B) add_active(p, n_active);
+    thin_finish<PHASE_B>(p, n_active, fails, a0, b0, own_c, a0, b0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1084,11 +1237,12 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
     const int vb = tid % TB, vr = tid / TB;
     const bool has_v = tid < NV;
     EpiIn in[RECT_SEG];
+    const uint8_t own_c = blk_own_load<PHASE_B>(p, a0, b0);
     if (has_v) {
 #pragma unroll
         for (int j = 0; j < RECT_SEG; ++j) {
             const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
-            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, y, x, (size_t)y * p.W + x);
         }
     }
     load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
@@ -1180,16 +1334,17 @@ __device__ __forceinline__ void rect_tile(const PhaseArgs& p, int a0, int b0, fl
     }
     // epilogue
     int n_active = 0;
+    uint64_t fails = 0;
     const float w = as_const(p.spans)[0].w0;
 #pragma unroll
     for (int j = 0; j < RECT_SEG; ++j) {
         int act = 0;
         const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
         if (has_v && y < p.H && x < p.W)
-            act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, in[j], w * v[j]);
-        if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+            act = epi_apply<PHASE_B>(p, y, x, (size_t)y * p.W + x, in[j], w * v[j], fails);
+        if (PHASE_B && p.cnt && !p.blk_lg) n_active += __popcll(__ballot(act));
     }
-    if (PHASE_B) add_active(p, n_active);
+    thin_finish<PHASE_B>(p, n_active, fails, a0, b0, own_c, a0, b0);
 }
 
 template <int S, int NW, bool PHASE_B>
@@ -1239,11 +1394,12 @@ __device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, flo
     const int vb = tid % TB, vr = tid / TB;
     const bool has_v = tid < NV;
     EpiIn in[RECT_SEG];
+    const uint8_t own_c = blk_own_load<PHASE_B>(p, a0, b0);
     if (has_v) {
 #pragma unroll
         for (int j = 0; j < RECT_SEG; ++j) {
             const int y = a0 + vr * RECT_SEG + j, x = b0 + vb;
-            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, (size_t)y * p.W + x);
+            if (y < p.H && x < p.W) in[j] = epi_load<PHASE_B>(p, y, x, (size_t)y * p.W + x);
         }
     }
     load_tile(lds, p.src, p.H, p.W, p.bc, a0 + p.lane_min, b0 + p.c_min, ny, nx, pitch);
@@ -1328,6 +1484,7 @@ __device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, flo
     const float w = as_const(p.spans)[0].w0;
     auto cnt_at = [&](int i, int j) { return (i < 0 || j < 0) ? 0 : N[i * pitch + j]; };
     int n_active = 0;
+    uint64_t fails = 0;
 #pragma unroll
     for (int j = 0; j < RECT_SEG; ++j) {
         int act = 0;
@@ -1342,11 +1499,11 @@ __device__ __forceinline__ void sat_tile(const PhaseArgs& p, int a0, int b0, flo
                               (cnt_at(a + kh - 1, vb - 1) - cnt_at(a - 1, vb - 1));
                 if (n == 0) v = 0.f;
             }
-            act = epi_apply<PHASE_B>(p, (size_t)y * p.W + x, in[j], w * v);
+            act = epi_apply<PHASE_B>(p, y, x, (size_t)y * p.W + x, in[j], w * v, fails);
         }
-        if (PHASE_B && p.cnt) n_active += __popcll(__ballot(act));
+        if (PHASE_B && p.cnt && !p.blk_lg) n_active += __popcll(__ballot(act));
     }
-    if (PHASE_B) add_active(p, n_active);
+    thin_finish<PHASE_B>(p, n_active, fails, a0, b0, own_c, a0, b0);
 }
 
 template <int S, int NW, bool PHASE_B>
@@ -1955,9 +2112,12 @@ __global__ __launch_bounds__(256) void thin_scatter_kernel(ThinListArgs a) {
     if (act) a.plist[base + __popcll(below)] = (int32_t)p;
 }
 
-// Tile list: ascending ids of flagged tiles (one workgroup), and clear the flags.
+// Tile list: ascending ids of flagged tiles (one workgroup); clear = 1 also clears the
+// flags (per-pixel rule: thin_count sets them afresh), clear = 0 keeps them (block rule:
+// they are the tiles' live activity flags).
 __global__ __launch_bounds__(1024) void tile_compact_kernel(int32_t* tflag, int n,
-                                                            int32_t* tlist, int64_t* count) {
+                                                            int32_t* tlist, int64_t* count,
+                                                            int clear) {
     __shared__ int wsum[16];
     __shared__ int base_s;
     if (threadIdx.x == 0) base_s = 0;
@@ -1974,7 +2134,7 @@ __global__ __launch_bounds__(1024) void tile_compact_kernel(int32_t* tflag, int 
         unsigned long long below = lane ? (m & ((~0ull) >> (64 - lane))) : 0ull;
         if (on) {
             tlist[base + __popcll(below)] = t;
-            tflag[t] = 0;
+            if (clear) tflag[t] = 0;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1985,6 +2145,47 @@ __global__ __launch_bounds__(1024) void tile_compact_kernel(int32_t* tflag, int 
         __syncthreads();
     }
     if (threadIdx.x == 0) *count = base_s;
+}
+
+// Block rule (counters per block of 2^lg pixels a side): set the flag of each 64 x 64 tile
+// to 1 if it holds an active block (counter < hyst), else 0, one thread per tile.  Tile t covers lane-axis tile
+// t % tiles_a and strip-axis tile t / tiles_a, rows for ORIENT_ROWS, columns otherwise.
+__global__ __launch_bounds__(256) void block_tiles_kernel(const uint8_t* cntb, int H, int W,
+                                                          int lg, int bw, int hyst, int orient,
+                                                          int tiles_a, int n_tiles,
+                                                          int32_t* tflag) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int ta = t % tiles_a, tb = t / tiles_a;
+    const int y0 = (orient == ORIENT_ROWS ? ta : tb) * 64;
+    const int x0 = (orient == ORIENT_ROWS ? tb : ta) * 64;
+    const int by1 = min(y0 + 64, H), bx1 = min(x0 + 64, W);
+    int on = 0;
+    for (int y = y0; y < by1; y += 1 << lg)
+        for (int x = x0; x < bx1; x += 1 << lg)
+            on |= (int)cntb[(size_t)(y >> lg) * bw + (x >> lg)] < hyst;
+    tflag[t] = on;
+}
+
+// Block rule: every pixel's counter from its block's (get_state, statistics and the
+// per-pixel list), and back: each block's counter from its top-left pixel (set_state).
+__global__ __launch_bounds__(256) void block_expand_kernel(const uint8_t* cntb, uint8_t* cnt,
+                                                           int64_t N, int W, int lg, int bw) {
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * 256) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        cnt[p] = cntb[(size_t)(y >> lg) * bw + (x >> lg)];
+    }
+}
+
+__global__ __launch_bounds__(256) void block_compress_kernel(const uint8_t* cnt, uint8_t* cntb,
+                                                             int W, int lg, int bw,
+                                                             int64_t n_blocks) {
+    for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < n_blocks;
+         b += (int64_t)gridDim.x * 256) {
+        const int64_t by = b / bw, bx = b - by * bw;
+        cntb[b] = cnt[(by << lg) * W + (bx << lg)];
+    }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -38,6 +38,7 @@ def make_params(f, psf, boundary="reflect", path="auto", schedule="auto", kahan=
         p.thin.reset_period = int(thin.get("reset_period", 10))
         p.thin.compact_period = int(thin.get("compact_period", 10))
         p.thin.keep_list = 1 if thin.get("keep_list", False) else 0
+        p.thin.block = int(thin.get("block", 0))
     p.stream = _stream_ptr(stream)
     if tuning:
         p.tuning.strip = int(tuning.get("strip", 0))

@@ -107,6 +107,7 @@ def request_footprint(req, device):
         p.thin.reset_period = int(req.thin.get("reset_period", 10))
         p.thin.compact_period = int(req.thin.get("compact_period", 10))
         p.thin.keep_list = 1 if req.thin.get("keep_list", False) else 0
+        p.thin.block = int(req.thin.get("block", 0))
     ws = A.rl_workspace_bytes(p)
     return ws + 2 * H * W * 4
 
