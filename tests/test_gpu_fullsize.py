@@ -146,3 +146,54 @@ def test_config3_full_size_lockstep(orc, k0):
     assert not mism.any(), f"{int(mism.sum())} counters differ from the float32 decision"
     differ = (c != gc) & active
     print(f"k0={k0} active={n_act} oracle-vs-GPU decisions differing: {int(differ.sum())}")
+
+
+@pytest.mark.parametrize("B,k0", [(64, 11), (16, 20)])
+def test_config3_full_size_lockstep_block_rule(orc, B, k0):
+    """The block rule at configuration 3's full size: one iteration from a seeded state
+    whose block counters freeze about 60 % of the blocks (k0 = 11 uses the tile list and
+    the tile flags, k0 = 20 is a full step); floats against the oracle's step, block
+    counters bit for bit against the float32 test on the GPU's own values."""
+    job = synth.job_for_config(3)[0]
+    f, h = job["f"], job["psf"]
+    thin = dict(job["thin"], block=B)
+    H, W = f.shape
+    rng = np.random.default_rng(304 + B)
+    u32 = (f * (1.0 + 0.01 * rng.standard_normal(f.shape))).clip(1e-3).astype(np.float32)
+    r32 = (1.0 + 0.05 * rng.standard_normal(f.shape)).clip(0.5).astype(np.float32)
+    hyst = thin["hysteresis"]
+    TY, TX = -(-H // B), -(-W // B)
+    frozen_b = rng.random((TY, TX)) < 0.6
+    cb = np.where(frozen_b, rng.integers(hyst, 40, (TY, TX)), rng.integers(0, hyst, (TY, TX)))
+    cb = cb.astype(np.uint8)
+    cnt = np.kron(cb, np.ones((B, B), np.uint8))[:H, :W].copy()
+    full = k0 % thin["reset_period"] == 0
+    act_b = np.ones(cb.shape, bool) if full else cb < hyst
+    active = np.kron(act_b, np.ones((B, B), bool))[:H, :W]
+    u = u32.astype(np.float64)
+    r = r32.astype(np.float64)
+    c = cnt.copy()
+    n_act = orc.thin_step(f, u, r, c, h, k0, thin)
+    assert n_act == int(active.sum())
+    g = Job(to_dev(f), h, thin=thin)
+    g.set_state(u=to_dev(u32), r=to_dev(r32), cnt=to_dev(cnt), k=k0)
+    g.iterate(1)
+    st = g.get_state()
+    sched = g.thin_schedule()
+    gu, gr, gc = (st["u"].cpu().numpy(), st["r"].cpu().numpy(), st["cnt"].cpu().numpy())
+    g.close()
+    assert rel_err(gu, u) <= RTOL
+    assert rel_err(gr[active], r[active]) <= RTOL
+    assert np.array_equal(gu[~active], u32[~active])
+    assert np.array_equal(gr[~active], r32[~active])
+    assert sched[-1] == n_act
+    below = orc.below_many(gu, u32, thin["mode"], thin["tau"])
+    pad = np.ones((TY * B, TX * B), bool)
+    pad[:H, :W] = below
+    passed = pad.reshape(TY, B, TX, B).all(axis=(1, 3))
+    up = np.minimum(cb.astype(np.int32) + 1, 255).astype(np.uint8)
+    want_b = np.where(act_b, np.where(passed, up, np.uint8(0)), cb).astype(np.uint8)
+    want = np.kron(want_b, np.ones((B, B), np.uint8))[:H, :W]
+    mism = gc != want
+    assert not mism.any(), f"{int(mism.sum())} counters differ from the float32 block decision"
+    print(f"B={B} k0={k0} active={n_act} blocks frozen {int((~act_b).sum())}")
