@@ -267,6 +267,10 @@ rl_status rl_solve_static(const rl_params *p, int32_t n_iter, float *u_out, rl_s
  * before this one's work has started on the stream (the library waits for its own
  * previous upload into the same `bws`).  A job may appear at most once (RL_E_INVAL).
  * Results per job are bit-identical to rl_iterate on that job alone.
+ * Streams: the kernel groups run concurrently on library-owned side streams (created once
+ * per process at the default priority), forked from `stream` by an event before the first
+ * launch and joined back into it by events after the last, so that all of the call's work
+ * is ordered on `stream` as if it ran there; the caller supplies no other stream.
  */
 rl_status rl_batch_workspace_bytes(int32_t n_jobs, size_t *bytes);
 rl_status rl_iterate_batch(rl_job *const *jobs, const int32_t *n_iter, int32_t n_jobs,
