@@ -4,7 +4,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
 
 #include "rl.h"
 
@@ -113,26 +112,37 @@ static inline void tap_offset(int i, int j, int oy, int ox, bool adjoint, int* s
 OpTable build_op_table(const float* psf, int kh, int kw, bool adjoint, Orient o,
                        bool split_uniform, int lmax) {
     const int oy = kh / 2, ox = kw / 2;
-    // line id (lane offset) -> list of (position along the line, weight)
-    std::map<int, std::vector<std::pair<int, float>>> lines;
-    for (int i = 0; i < kh; ++i)
-        for (int j = 0; j < kw; ++j) {
-            float v = psf[i * kw + j];
+    // Lines are PSF rows (Orient::Rows) or columns (Orient::Cols), visited in ascending lane
+    // offset, and the taps of a line in ascending position: tap (i, j) sits at lane offset /
+    // position (sy, sx) of tap_offset, which ascend with i and j for the adjoint and descend
+    // for conv, so conv walks both indices backwards.  No sorting and no per-line containers.
+    const bool rows = o == Orient::Rows;
+    const int nl = rows ? kh : kw, np = rows ? kw : kh;
+    OpTable t;
+    bool first = true;
+    std::vector<std::pair<int, float>> taps;
+    taps.reserve((size_t)np);
+    std::vector<Span> pieces;
+    for (int li = 0; li < nl; ++li) {
+        const int idx = adjoint ? li : nl - 1 - li;
+        taps.clear();
+        for (int pi = 0; pi < np; ++pi) {
+            const int pidx = adjoint ? pi : np - 1 - pi;
+            const int i = rows ? idx : pidx, j = rows ? pidx : idx;
+            const float v = psf[i * kw + j];
             if (v == 0.f) continue;
             int sy, sx;
             tap_offset(i, j, oy, ox, adjoint, &sy, &sx);
-            if (o == Orient::Rows) lines[sy].push_back({sx, v});
-            else lines[sx].push_back({sy, v});
+            taps.push_back({rows ? sx : sy, v});
         }
-    OpTable t;
-    bool first = true;
-    for (auto& kv : lines) {
-        auto& taps = kv.second;
-        std::sort(taps.begin(), taps.end(),
-                  [](const std::pair<int, float>& a, const std::pair<int, float>& b) {
-                      return a.first < b.first;
-                  });
-        std::vector<Span> pieces;
+        if (taps.empty()) continue;
+        int lane;
+        {
+            int sy, sx;
+            tap_offset(rows ? idx : 0, rows ? 0 : idx, oy, ox, adjoint, &sy, &sx);
+            lane = rows ? sy : sx;
+        }
+        pieces.clear();
         size_t q = 0;
         while (q < taps.size()) {
             size_t q1 = q;
@@ -145,7 +155,7 @@ OpTable build_op_table(const float* psf, int kh, int kw, bool adjoint, Orient o,
                 size_t e = q1;
                 if (lmax > 0 && e - s + 1 > (size_t)lmax) e = s + lmax - 1;
                 Span sp{};
-                sp.lane_off = kv.first;
+                sp.lane_off = lane;
                 sp.c0 = taps[s].first;
                 sp.len = (int32_t)(e - s + 1);
                 sp.woff = (int32_t)t.w.size();

@@ -524,6 +524,32 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     return RL_OK;
 }
 
+// The configuration chosen by the last rl_workspace_bytes call on this thread, reused by
+// an rl_init with the same parameters and PSF: callers size the workspace first and then
+// initialise, so each job runs the PSF compiler's search once.  The key is the parameter
+// block with its pointers cleared, the PSF values and the tuning-cache generation (a
+// change of the cache can change the choice).
+std::atomic<uint64_t> g_tune_gen{0};
+struct ConfigMemo {
+    std::string key;
+    Config cfg;
+    bool valid = false;
+};
+thread_local ConfigMemo g_memo;
+
+std::string config_key(const rl_params* p) {
+    rl_params q = *p;
+    q.f = nullptr;
+    q.u0 = nullptr;
+    q.psf = nullptr;
+    q.stream = nullptr;
+    const uint64_t gen = g_tune_gen.load();
+    std::string k(reinterpret_cast<const char*>(&q), sizeof q);
+    k.append(reinterpret_cast<const char*>(&gen), sizeof gen);
+    k.append(reinterpret_cast<const char*>(p->psf), (size_t)p->psf_h * p->psf_w * sizeof(float));
+    return k;
+}
+
 Layout make_layout(const rl_params* p, const Config& cfg) {
     Layout L{};
     const size_t N = (size_t)p->height * p->width;
@@ -1351,6 +1377,9 @@ rl_status rl_workspace_bytes(const rl_params* p, size_t* bytes) {
     st = choose_config(p, c, &cfg, &why);
     if (st) return st;
     *bytes = make_layout(p, cfg).total;
+    g_memo.key = config_key(p);
+    g_memo.cfg = std::move(cfg);
+    g_memo.valid = true;
     return RL_OK;
 }
 
@@ -1385,8 +1414,12 @@ rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, 
     j->list_valid = false;
     j->pending_finalize = false;
     j->live = true;
-    st = choose_config(p, c, &j->cfg, &why);
-    if (st) { delete j; return st; }
+    if (g_memo.valid && g_memo.key == config_key(p)) {
+        j->cfg = g_memo.cfg;
+    } else {
+        st = choose_config(p, c, &j->cfg, &why);
+        if (st) { delete j; return st; }
+    }
     j->L = make_layout(p, j->cfg);
     if (ws_bytes < j->L.total) { delete j; return RL_E_NOMEM; }
     j->ws = static_cast<char*>(ws);
@@ -2069,6 +2102,7 @@ rl_status rl_autotune(const rl_params* p, void* ws, size_t ws_bytes, int32_t n_i
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[tune_key(p, c)] = bestt;
+        ++g_tune_gen;
     }
     *best = bestt.t;
     if (best_schedule) *best_schedule = bestt.schedule;
@@ -2127,12 +2161,14 @@ rl_status rl_tune_cache_load(const char* path) {
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : loaded) g_tune[kv.first] = kv.second;
+    ++g_tune_gen;
     return RL_OK;
 }
 
 rl_status rl_tune_cache_clear(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+    ++g_tune_gen;
     return RL_OK;
 }
 
