@@ -730,11 +730,12 @@ def report_serving(args, dev):
 def _timing_name(kernel):
     """Map a rocprofv3 kernel symbol to the library's timing-registry name."""
     import re
-    m = re.search(r"rlk::(slide|span|resident|rect|sat|mixed|mfma)_kernel<([^>]*)>", kernel)
+    m = re.search(r"rlk::(slide|span|resident|resident_multi|rect|sat|mixed|mfma)_kernel<([^>]*)>",
+                  kernel)
     if not m:
         return None
     kind, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
-    if kind == "resident":
+    if kind in ("resident", "resident_multi"):
         return "resident_box"
     phase_b = targs[-1] == "true"
     if kind == "span" and targs[2] == "1":

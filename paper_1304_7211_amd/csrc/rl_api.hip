@@ -861,6 +861,22 @@ ResFn resident_fn(int orient, int seg) {
     return nullptr;
 }
 
+using ResMultiFn = void (*)(const ResidentArgs*, const int32_t*, int);
+ResMultiFn resident_multi_fn(int orient, int seg) {
+#define RL_RES(O)                                              \
+    switch (seg) {                                             \
+        case 2: return rlk::resident_multi_kernel<O, 2>;       \
+        case 4: return rlk::resident_multi_kernel<O, 4>;       \
+        case 8: return rlk::resident_multi_kernel<O, 8>;       \
+        case 16: return rlk::resident_multi_kernel<O, 16>;     \
+        case 32: return rlk::resident_multi_kernel<O, 32>;     \
+    }
+    if (orient == rlk::ORIENT_ROWS) { RL_RES(rlk::ORIENT_ROWS) }
+    else { RL_RES(rlk::ORIENT_COLS) }
+#undef RL_RES
+    return nullptr;
+}
+
 // Device table entry of one phase of a job (base iteration index k0).
 PhaseArgs phase_args(rl_job* j, bool phase_b, int64_t k0) {
     PhaseArgs a{};
@@ -1046,29 +1062,40 @@ rl_status capture_graph(rl_job* j, int n) {
     return st;
 }
 
+// Arguments of n resident iterations of a job (KIND_RESIDENT).
+ResidentArgs resident_args(const rl_job* j, int32_t n) {
+    const Config& c = j->cfg;
+    ResidentArgs a{};
+    a.H = j->H;
+    a.W = j->W;
+    a.bc = j->p.boundary;
+    a.kahan = j->p.kahan;
+    a.u = j->at<float>(j->L.u);
+    a.f = j->at<float>(j->L.f);
+    a.n_iter = n;
+    a.lines_per_wg = c.lines_per_wg;
+    a.wpl = c.wpl;
+    a.conv_c0 = j->psf.box_c0;
+    a.len = j->psf.box_len;
+    // adjoint window = mirror of the forward window
+    a.corr_c0 = -(j->psf.box_c0 + j->psf.box_len - 1);
+    a.w = j->psf.box_w;
+    a.halo = j->psf.box_len - 1;
+    a.line_words = c.line_words;
+    return a;
+}
+
+int32_t resident_workgroups(const Config& c) {
+    return (int32_t)((c.lines + c.lines_per_wg - 1) / c.lines_per_wg);
+}
+
 rl_status enqueue_iterations(rl_job* j, int32_t n) {
     const Config& c = j->cfg;
     hipStream_t s = j->stream;
     if (c.kind == KIND_RESIDENT) {
         if (n == 0) return RL_OK;
-        ResidentArgs a{};
-        a.H = j->H;
-        a.W = j->W;
-        a.bc = j->p.boundary;
-        a.kahan = j->p.kahan;
-        a.u = j->at<float>(j->L.u);
-        a.f = j->at<float>(j->L.f);
-        a.n_iter = n;
-        a.lines_per_wg = c.lines_per_wg;
-        a.wpl = c.wpl;
-        a.conv_c0 = j->psf.box_c0;
-        a.len = j->psf.box_len;
-        // adjoint window = mirror of the forward window
-        a.corr_c0 = -(j->psf.box_c0 + j->psf.box_len - 1);
-        a.w = j->psf.box_w;
-        a.halo = j->psf.box_len - 1;
-        a.line_words = c.line_words;
-        unsigned grid = (unsigned)((c.lines + c.lines_per_wg - 1) / c.lines_per_wg);
+        const ResidentArgs a = resident_args(j, n);
+        unsigned grid = (unsigned)resident_workgroups(c);
         unsigned block = (unsigned)(c.lines_per_wg * 64 * c.wpl);
         rl_status st = dev_err(launch("resident_box", resident_fn(c.orient, c.seg), dim3(grid),
                                       dim3(block), c.lds_a, s, a), "resident_box");
@@ -1680,14 +1707,21 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     rl_status st;
-    std::vector<int> tiled, resident;
+    // tiled two-pass jobs (shared launches per kernel variant), resident line solvers
+    // (shared launches per line orientation and segment length), and fused or robust jobs
+    // (their own launches)
+    std::vector<int> tiled, resident, other;
     for (int32_t i = 0; i < n_jobs; ++i) {
-        if (jobs[i]->cfg.kind == KIND_RESIDENT || jobs[i]->cfg.kind == KIND_FUSED ||
-            jobs[i]->p.rob_eps > 0.f)
-            resident.push_back(i);
-        else tiled.push_back(i);
+        const rl_job* j = jobs[i];
+        if (j->cfg.kind == KIND_RESIDENT) {
+            if (n_iter[i] > 0) resident.push_back(i);
+        } else if (j->cfg.kind == KIND_FUSED || j->p.rob_eps > 0.f) {
+            other.push_back(i);
+        } else {
+            tiled.push_back(i);
+        }
     }
-    if (tiled.empty() && resident.empty()) return RL_OK;
+    if (tiled.empty() && resident.empty() && other.empty()) return RL_OK;
     // group by kernel variant; inside a group, jobs with more iterations left come first,
     // so the jobs still running at batch iteration kb are always a prefix of the group
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
@@ -1715,6 +1749,7 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         total_work += work[i];
     }
     for (int i : resident) total_work += resident_work_us(jobs[i], n_iter[i]);
+    for (int i : other) total_work += resident_work_us(jobs[i], n_iter[i]);
     const double share = total_work / (2.0 * kBatchStreams);
     std::vector<std::vector<int>> chunks;
     for (auto& kv : groups) {
@@ -1759,6 +1794,35 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         off = align_up(off + g.prefix.size() * sizeof(int32_t));
         gs.push_back(std::move(g));
     }
+    // resident groups: one launch per (orientation, segment length) runs every iteration
+    // of all its jobs, each workgroup its own job's count
+    struct RG {
+        std::vector<int> idx;
+        std::vector<int32_t> prefix;
+        size_t off_t = 0, off_p = 0, lds = 0;
+        int orient = 0, seg = 0;
+        double w = 0.0;
+    };
+    std::map<std::pair<int, int>, std::vector<int>> rmap;
+    for (int i : resident) rmap[std::make_pair(jobs[i]->cfg.orient, jobs[i]->cfg.seg)].push_back(i);
+    std::vector<RG> rgs;
+    for (auto& kv : rmap) {
+        RG g;
+        g.idx = kv.second;
+        g.orient = kv.first.first;
+        g.seg = kv.first.second;
+        g.prefix.push_back(0);
+        for (int i : g.idx) {
+            g.prefix.push_back(g.prefix.back() + resident_workgroups(jobs[i]->cfg));
+            g.lds = std::max(g.lds, jobs[i]->cfg.lds_a);
+            g.w += resident_work_us(jobs[i], n_iter[i]);
+        }
+        g.off_t = off;
+        off = align_up(off + g.idx.size() * sizeof(ResidentArgs));
+        g.off_p = off;
+        off = align_up(off + g.prefix.size() * sizeof(int32_t));
+        rgs.push_back(std::move(g));
+    }
     // stage the tables on the host and copy them in; the staging buffer of this batch
     // workspace is reused only after its previous copy has completed
     {
@@ -1782,6 +1846,11 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
             }
             std::memcpy(bs.host.data() + g.off_p, g.prefix.data(), g.prefix.size() * sizeof(int32_t));
         }
+        for (const RG& g : rgs) {
+            ResidentArgs* t = reinterpret_cast<ResidentArgs*>(bs.host.data() + g.off_t);
+            for (size_t q = 0; q < g.idx.size(); ++q) t[q] = resident_args(jobs[g.idx[q]], n_iter[g.idx[q]]);
+            std::memcpy(bs.host.data() + g.off_p, g.prefix.data(), g.prefix.size() * sizeof(int32_t));
+        }
         hipError_t e = off ? hipMemcpyAsync(bws, bs.host.data(), off, hipMemcpyHostToDevice, s)
                            : hipSuccess;
         if (e == hipSuccess) e = hipEventRecord(bs.done, s);
@@ -1792,24 +1861,30 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     // streams (no more than the device's hardware queues, so that streams do not share a
     // queue and serialise behind each other), longest estimated work first, each to the
     // stream with the least work so far
-    std::vector<std::pair<double, int>> items;  // (estimated us, group index or -1 - job)
+    struct Item {
+        double w;    // estimated us
+        int kind;    // 0: tiled group, 1: resident group, 2: job on its own launches
+        int index;
+    };
+    std::vector<Item> items;
     for (size_t gi = 0; gi < gs.size(); ++gi) {
         double w = 20.0 * n_iter[gs[gi].idx[0]];
         for (int i : gs[gi].idx) w += 5.8e-8 * unit_cost(jobs[i]->cfg) * (double)jobs[i]->N * n_iter[i];
-        items.emplace_back(w, (int)gi);
+        items.push_back(Item{w, 0, (int)gi});
     }
-    for (int i : resident) items.emplace_back(resident_work_us(jobs[i], n_iter[i]), -1 - i);
-    std::stable_sort(items.begin(), items.end(),
-                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+    for (size_t ri = 0; ri < rgs.size(); ++ri) items.push_back(Item{rgs[ri].w, 1, (int)ri});
+    for (int i : other) items.push_back(Item{resident_work_us(jobs[i], n_iter[i]), 2, i});
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.w > b.w; });
     const int n_streams = std::min<int>(kBatchStreams, (int)items.size());
     std::vector<double> load(n_streams, 0.0);
-    std::vector<int> group_stream(gs.size(), 0);
-    std::vector<std::pair<int, int>> resident_stream;  // (job, stream)
-    for (const auto& it : items) {
+    std::vector<int> group_stream(gs.size(), 0), rgroup_stream(rgs.size(), 0);
+    std::vector<std::pair<int, int>> other_stream;  // (job, stream)
+    for (const Item& it : items) {
         const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[q] += it.first;
-        if (it.second >= 0) group_stream[it.second] = q;
-        else resident_stream.emplace_back(-1 - it.second, q);
+        load[q] += it.w;
+        if (it.kind == 0) group_stream[it.index] = q;
+        else if (it.kind == 1) rgroup_stream[it.index] = q;
+        else other_stream.emplace_back(it.index, q);
     }
     if ((st = side_streams(n_streams))) return st;
     std::lock_guard<std::mutex> lk(g_smu);
@@ -1817,9 +1892,20 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     for (int q = 0; q < n_streams; ++q)
         if ((st = dev_err(hipStreamWaitEvent(g_side[q], g_fork, 0), "fork wait"))) return st;
     auto stream_of_group = [&](size_t gi) { return g_side[group_stream[gi]]; };
-    // jobs on the resident schedule run all their iterations in one launch each; fused
-    // jobs one launch per iteration, on their side stream
-    for (const auto& rq : resident_stream) {
+    char* base = static_cast<char*>(bws);
+    // resident groups: all iterations of all their jobs in one launch each
+    for (size_t ri = 0; ri < rgs.size(); ++ri) {
+        const RG& g = rgs[ri];
+        st = dev_err(launch("resident_box", resident_multi_fn(g.orient, g.seg), dim3(g.prefix.back()),
+                            dim3(256), g.lds, g_side[rgroup_stream[ri]],
+                            reinterpret_cast<const ResidentArgs*>(base + g.off_t),
+                            reinterpret_cast<const int32_t*>(base + g.off_p), (int)g.idx.size()),
+                     "resident_box");
+        if (st) return st;
+        for (int i : g.idx) jobs[i]->k += n_iter[i];
+    }
+    // fused jobs one launch per iteration, robust ones four, on their side stream
+    for (const auto& rq : other_stream) {
         rl_job* j = jobs[rq.first];
         hipStream_t keep = j->stream;
         j->stream = g_side[rq.second];
@@ -1827,7 +1913,6 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
         j->stream = keep;
         if (st) return st;
     }
-    char* base = static_cast<char*>(bws);
     for (size_t gi = 0; gi < gs.size(); ++gi) {
         const G& g = gs[gi];
         hipStream_t gsm = stream_of_group(gi);

@@ -1958,17 +1958,15 @@ __device__ __forceinline__ void box_segment(const float* line, int halo, int p0,
     }
 }
 
+// All iterations of one job's lines wg * lines_per_wg .. on chip (see resident_kernel).
+// Threads past the job's lines_per_wg * 64 * wpl take part in the barriers only.
 template <int ORIENT, int SEG>
-__global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void resident_body(const ResidentArgs& a, int wg, float* lds) {
     const int n = (ORIENT == ORIENT_ROWS) ? a.W : a.H;       // line length
     const int m = (ORIENT == ORIENT_ROWS) ? a.H : a.W;       // number of lines
     const int tpl = 64 * a.wpl;                               // threads per line
     const int j = threadIdx.x / tpl;                          // line within the workgroup
     const int t = threadIdx.x % tpl;                          // segment within the line
-    // neighbouring lines share cache lines (column lines especially): give each XCD a
-    // contiguous range of workgroups so those lines are fetched once per XCD
-    const int wg = xcd_tile(blockIdx.x, gridDim.x);
     const int line = wg * a.lines_per_wg + j;
     const bool live = (j < a.lines_per_wg) && (line < m);
     const int halo = a.halo;
@@ -2030,6 +2028,40 @@ __global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
             if (pos < n) a.u[gidx(pos)] = ul[line_idx<SEG>(pos, halo)];
         }
     }
+}
+
+// Neighbouring lines share cache lines (column lines especially): each XCD gets a
+// contiguous range of workgroups, so that those lines are fetched once per XCD.
+template <int ORIENT, int SEG>
+__global__ __launch_bounds__(256) void resident_kernel(ResidentArgs a) {
+    extern __shared__ float lds[];
+    resident_body<ORIENT, SEG>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+// Several resident jobs of one line orientation and segment length in one launch (batches):
+// job j owns workgroups [prefix[j], prefix[j + 1]) of the XCD-ordered index, and each
+// workgroup runs its own job's iteration count.
+typedef const __attribute__((address_space(4))) ResidentArgs* ConstResPtr;
+template <int ORIENT, int SEG>
+__global__ __launch_bounds__(256) void resident_multi_kernel(const ResidentArgs* table,
+                                                             const int32_t* prefix, int n_jobs) {
+    extern __shared__ float lds[];
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const ConstIntPtr pre = (ConstIntPtr)prefix;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {  // last job with prefix <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ConstResPtr t = (ConstResPtr)table + lo;
+    ResidentArgs a;
+    a.H = t->H; a.W = t->W; a.bc = t->bc; a.kahan = t->kahan;
+    a.u = t->u; a.f = t->f; a.n_iter = t->n_iter;
+    a.lines_per_wg = t->lines_per_wg; a.wpl = t->wpl;
+    a.conv_c0 = t->conv_c0; a.corr_c0 = t->corr_c0; a.len = t->len;
+    a.halo = t->halo; a.line_words = t->line_words; a.w = t->w;
+    resident_body<ORIENT, SEG>(a, b - pre[lo], lds);
 }
 
 // ---------------------------------------------------------------------------------------

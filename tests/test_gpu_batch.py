@@ -28,6 +28,11 @@ def _mixed_jobs():
         ("dense15", 129, 130, synth.dense_random(15, 5), {}, 7),
         ("vbox9_tp", 160, 96, synth.box_v(9), dict(schedule="two_pass"), 12),
         ("hbox31_res", 64, 250, synth.box_h(31), {}, 13),
+        # more resident line solvers: jobs of one line orientation share a launch, each
+        # workgroup running its own job's iteration count
+        ("hbox15_res", 90, 200, synth.box_h(15), {}, 9),
+        ("vbox21_res", 220, 70, synth.box_v(21), {}, 17),
+        ("vbox7_res", 130, 128, synth.box_v(7), {}, 6),
         ("disc5_thin", 140, 150, synth.disc(5), dict(thin=THIN), 25),
         ("obl15_thin", 120, 90, synth.oblique_line(15, 60.0), dict(thin=THIN), 16),
         ("rect9x5", 170, 140, synth.box_rect(9, 5), {}, 10),
