@@ -17,8 +17,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off for all device code (some v_pk_* FP32 forms
 # have been seen to give wrong results without any error); the host pass warns that it
 # does not know the feature, which is harmless.
+# The matrix-core kernel's accumulators are kept in ordinary VGPRs (the VGPR form of the
+# MFMA instructions): with accumulation registers the compiler copied every accumulator
+# between the two register files on each PSF line.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-Wno-unused-command-line-argument",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 SOURCES = [os.path.join(CSRC, "rl_api.hip"), os.path.join(CSRC, "psf_compile.cpp")]

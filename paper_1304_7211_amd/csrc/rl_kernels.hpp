@@ -913,20 +913,19 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     const bf16x8* tab = reinterpret_cast<const bf16x8*>(p.wts);
     bf16x8 nw1 = tab[lane], nw2 = tab[64 + lane], nw3 = tab[128 + lane];
     const __bf16* base = lds + (16 * wv + m) * MF_PITCH + 8 * q;
-    for (int di = 0; di < lines; ++di) {
+    // one PSF line: its leading products into acc, the five smaller ones into small
+    auto line = [&](int di, f32x4 (&acc)[4]) {
         const bf16x8 w1 = nw1, w2 = nw2, w3 = nw3;
         nw1 = tab[(3 * di + 3) * 64 + lane];
         nw2 = tab[(3 * di + 4) * 64 + lane];
         nw3 = tab[(3 * di + 5) * 64 + lane];
         const __bf16* rp = base + di * MF_PITCH;
-        const bool odd_line = (di & 1) != 0;
 #pragma unroll
         for (int bx = 0; bx < 4; ++bx) {
             const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(rp + 16 * bx);
             const bf16x8 x2 = *reinterpret_cast<const bf16x8*>(rp + plane + 16 * bx);
             const bf16x8 x3 = *reinterpret_cast<const bf16x8*>(rp + 2 * plane + 16 * bx);
-            if (odd_line) odd[bx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w1, odd[bx], 0, 0, 0);
-            else even[bx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w1, even[bx], 0, 0, 0);
+            acc[bx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w1, acc[bx], 0, 0, 0);
             f32x4 sm = small[bx];
             sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, w2, sm, 0, 0, 0);
             sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, w1, sm, 0, 0, 0);
@@ -935,7 +934,16 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
             sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x3, w1, sm, 0, 0, 0);
             small[bx] = sm;
         }
+    };
+    // even and odd lines in one loop trip, so that each accumulator set keeps its
+    // registers (selecting the accumulator per line made the compiler copy all of them
+    // between register files on every line)
+    int di = 0;
+    for (; di + 1 < lines; di += 2) {
+        line(di, even);
+        line(di + 1, odd);
     }
+    if (di < lines) line(di, even);
 
     int n_active = 0;
     uint64_t fails = 0;
