@@ -826,9 +826,9 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 // A workgroup of MF_NW wavefronts owns a 64 x 64 output tile; wavefront w computes rows
 // 16 w .. 16 w + 15 as four 16 x 16 blocks side by side, which share each line's weight
 // operand.  The source tile (PSF halo included, boundary fold applied) is converted once
-// into three bfloat16 planes in LDS with a row pitch of MF_PITCH elements (11 x 16 bytes):
-// the 16 rows that a 16-lane group reads with one 16-byte load start in distinct bank
-// quadruples.  Operand layout of v_mfma_f32_16x16x32_bf16 on a wavefront of 64: lane l
+// into three bfloat16 planes in LDS with a row pitch of MF_PITCH elements (10 x 16 bytes,
+// the unpadded row: of the pitches 80 .. 136 measured, 80 gave the fewest LDS bank-conflict
+// cycles on the operand loads, a ninth of those of 88).  Operand layout of v_mfma_f32_16x16x32_bf16 on a wavefront of 64: lane l
 // holds A[l % 16][8 (l / 16) + t] and B[8 (l / 16) + t][l % 16] for t < 8 and receives
 // D[4 (l / 16) + t][l % 16] for t < 4.  The weight operands (per line, per part, per lane:
 // 8 bfloat16 values) are built on the host; p.wts points to them.  The epilogue is the
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 constexpr int MF_NW = 4;
 constexpr int MF_T = 64;             // tile rows and columns
 constexpr int MF_NX = MF_T + 16;     // LDS columns: the last block reads 16 * 3 + 32
-constexpr int MF_PITCH = 88;         // LDS row pitch in bfloat16 elements
+constexpr int MF_PITCH = 80;         // LDS row pitch in bfloat16 elements
 constexpr int MF_MAXW = 17;          // widest PSF line (16 + MF_MAXW - 1 <= 32)
 constexpr int MF_MAXROWS = 64;       // most PSF lines
 constexpr int MF_SPITCH = 84;        // row pitch (floats) of the float32 staging tile
