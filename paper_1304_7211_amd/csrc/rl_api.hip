@@ -36,6 +36,10 @@ constexpr size_t kAlign = 256;
 // block rule's per-wavefront failure words, the persistent schedule's task slot)
 constexpr size_t kLdsLimit = 160 * 1024 - 256;
 constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
+// When the span and sliding kernels run four-wavefront workgroups (strips of 8): 0 never,
+// 1 where eight wavefronts would run strips of 4 (images below 0.5 Mpx), 2 also in place of
+// strips of 8 (64 x 32 tiles on every image)
+constexpr int kFourWave = 1;
 constexpr size_t kSpanPad = 2;  // zero descriptors after each span table (read-ahead)
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
@@ -54,6 +58,7 @@ std::vector<TimedLaunch> g_timed;
 
 struct Config {
     int path = 0, sched = 0, kind = 0, orient = 0, S = 16, lmax = 1;
+    int nw = kNW;            // wavefronts per workgroup of the span and sliding kernels
     int threads = kNW * 64;  // workgroup size of the phase kernels
     int TA = 64, TB = 64, tiles_a = 1, tiles_b = 1;
     int reach_a = 1, reach_b = 1;  // persistent schedule: tiles within the halo's reach
@@ -453,8 +458,18 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             cfg->corr = rl::build_op_table(h, kh, kw, true, o, split, lm);
         }
     }
+    // four-wavefront workgroups with strips of 8 in place of eight wavefronts with strips
+    // of 4: the same 64 x 32 tile, half the seeds and windows per output (span and sliding
+    // kernels with the default strip; the block rule needs 64 x 64 tiles, the persistent
+    // schedule runs eight wavefronts)
+    if (kFourWave && (cfg->kind == KIND_SPAN || cfg->kind == KIND_SLIDE) && !p->tuning.strip &&
+        !blk && sched != RL_SCHED_PERSISTENT && (cfg->S == 4 || (kFourWave == 2 && cfg->S == 8))) {
+        cfg->S = 8;
+        cfg->nw = 4;
+        cfg->threads = 4 * 64;
+    }
     cfg->TA = 64;
-    cfg->TB = cfg->kind == KIND_MFMA ? rlk::MF_T : kNW * cfg->S;
+    cfg->TB = cfg->kind == KIND_MFMA ? rlk::MF_T : cfg->nw * cfg->S;
     if (cfg->kind == KIND_MFMA) cfg->threads = rlk::MF_NW * 64;
     const int extra = 0;  // windows never read past the last tap of a piece
     auto lds_for = [&](const rl::OpTable& t) {
@@ -464,7 +479,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
             size_t na = 64 + t.lane_max - t.lane_min, nb = cfg->TB + t.c_max - t.c_min + extra;
             size_t ny = cfg->orient == rlk::ORIENT_ROWS ? na : nb;
             size_t nx = cfg->orient == rlk::ORIENT_ROWS ? nb : na;
-            b = std::max(b, (ny * (nx | 1) + rlk::slide_scratch_floats<kNW>()) * sizeof(float));
+            b = std::max(b, (ny * (nx | 1) + (size_t)(4 * cfg->nw * 64 + cfg->nw)) * sizeof(float));
         }
         if (cfg->kind == KIND_RECT) {
             // tile plus the horizontal window sums of every tile row
@@ -483,7 +498,7 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     cfg->lds_b = lds_for(cfg->corr);
     while (std::max(cfg->lds_a, cfg->lds_b) > kLdsLimit && cfg->kind == KIND_SLIDE && cfg->S > 8) {
         cfg->S /= 2;
-        cfg->TB = kNW * cfg->S;
+        cfg->TB = cfg->nw * cfg->S;
         cfg->lds_a = lds_for(cfg->conv);
         cfg->lds_b = lds_for(cfg->corr);
     }
@@ -730,29 +745,32 @@ unsigned grid_for(int64_t n, int64_t per = 256, int64_t cap = 4096) {
 // ---- kernel instantiation tables --------------------------------------------------------
 using PhaseFn = void (*)(rlk::LaunchArgs);
 
-template <int O, int S, bool B>
+template <int O, int S, int NW, bool B>
 PhaseFn span_fn(int lmax) {
     switch (lmax) {
-        case 1: return rlk::span_kernel<O, S, 1, kNW, B>;
-        case 4: return rlk::span_kernel<O, S, 4, kNW, B>;
-        case 8: return rlk::span_kernel<O, S, 8, kNW, B>;
-        case 16: return rlk::span_kernel<O, S, 16, kNW, B>;
+        case 1: return rlk::span_kernel<O, S, 1, NW, B>;
+        case 4: return rlk::span_kernel<O, S, 4, NW, B>;
+        case 8: return rlk::span_kernel<O, S, 8, NW, B>;
+        case 16: return rlk::span_kernel<O, S, 16, NW, B>;
     }
     return nullptr;
 }
 
+// nw = 4 (four-wavefront workgroups) exists for strips of 8 only
 template <int O, bool B>
-PhaseFn span_fn_s(int S, int lmax) {
+PhaseFn span_fn_s(int S, int lmax, int nw) {
+    if (nw == 4) return S == 8 ? span_fn<O, 8, 4, B>(lmax) : nullptr;
     switch (S) {
-        case 4: return span_fn<O, 4, B>(lmax);
-        case 8: return span_fn<O, 8, B>(lmax);
-        case 16: return span_fn<O, 16, B>(lmax);
+        case 4: return span_fn<O, 4, kNW, B>(lmax);
+        case 8: return span_fn<O, 8, kNW, B>(lmax);
+        case 16: return span_fn<O, 16, kNW, B>(lmax);
     }
     return nullptr;
 }
 
 template <int O, bool B>
-PhaseFn slide_fn(int S) {
+PhaseFn slide_fn(int S, int nw) {
+    if (nw == 4) return S == 8 ? rlk::slide_kernel<O, 8, 4, B> : nullptr;
     switch (S) {
         case 4: return rlk::slide_kernel<O, 4, kNW, B>;
         case 8: return rlk::slide_kernel<O, 8, kNW, B>;
@@ -825,14 +843,14 @@ PhaseFn phase_fn(const Config& c, bool phase_b) {
     }
     if (c.kind == KIND_SPAN) {
         if (c.orient == rlk::ORIENT_ROWS)
-            return phase_b ? span_fn_s<rlk::ORIENT_ROWS, true>(c.S, c.lmax)
-                           : span_fn_s<rlk::ORIENT_ROWS, false>(c.S, c.lmax);
-        return phase_b ? span_fn_s<rlk::ORIENT_COLS, true>(c.S, c.lmax)
-                       : span_fn_s<rlk::ORIENT_COLS, false>(c.S, c.lmax);
+            return phase_b ? span_fn_s<rlk::ORIENT_ROWS, true>(c.S, c.lmax, c.nw)
+                           : span_fn_s<rlk::ORIENT_ROWS, false>(c.S, c.lmax, c.nw);
+        return phase_b ? span_fn_s<rlk::ORIENT_COLS, true>(c.S, c.lmax, c.nw)
+                       : span_fn_s<rlk::ORIENT_COLS, false>(c.S, c.lmax, c.nw);
     }
     if (c.orient == rlk::ORIENT_ROWS)
-        return phase_b ? slide_fn<rlk::ORIENT_ROWS, true>(c.S) : slide_fn<rlk::ORIENT_ROWS, false>(c.S);
-    return phase_b ? slide_fn<rlk::ORIENT_COLS, true>(c.S) : slide_fn<rlk::ORIENT_COLS, false>(c.S);
+        return phase_b ? slide_fn<rlk::ORIENT_ROWS, true>(c.S, c.nw) : slide_fn<rlk::ORIENT_ROWS, false>(c.S, c.nw);
+    return phase_b ? slide_fn<rlk::ORIENT_COLS, true>(c.S, c.nw) : slide_fn<rlk::ORIENT_COLS, false>(c.S, c.nw);
 }
 
 const char* phase_name(const Config& c, bool phase_b) {
@@ -1724,10 +1742,10 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     if (tiled.empty() && resident.empty() && other.empty()) return RL_OK;
     // group by kernel variant; inside a group, jobs with more iterations left come first,
     // so the jobs still running at batch iteration kb are always a prefix of the group
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
     for (int i : tiled) {
         const Config& c = jobs[i]->cfg;
-        groups[std::make_tuple(c.kind, c.orient, c.S, c.lmax)].push_back(i);
+        groups[std::make_tuple(c.kind, c.orient, c.S, c.lmax, c.nw)].push_back(i);
     }
     struct G {
         std::vector<int> idx;
