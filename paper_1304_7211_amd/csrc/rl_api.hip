@@ -460,10 +460,10 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     }
     // four-wavefront workgroups with strips of 8 in place of eight wavefronts with strips
     // of 4: the same 64 x 32 tile, half the seeds and windows per output (span and sliding
-    // kernels with the default strip; the block rule needs 64 x 64 tiles, the persistent
-    // schedule runs eight wavefronts)
+    // kernels with the default strip, two-pass and persistent alike, so that the schedules
+    // keep giving the same results; the block rule needs 64 x 64 tiles)
     if (kFourWave && (cfg->kind == KIND_SPAN || cfg->kind == KIND_SLIDE) && !p->tuning.strip &&
-        !blk && sched != RL_SCHED_PERSISTENT && (cfg->S == 4 || (kFourWave == 2 && cfg->S == 8))) {
+        !blk && (cfg->S == 4 || (kFourWave == 2 && cfg->S == 8))) {
         cfg->S = 8;
         cfg->nw = 4;
         cfg->threads = 4 * 64;
@@ -782,43 +782,44 @@ PhaseFn slide_fn(int S, int nw) {
 
 using PersistFn = void (*)(rlk::PersistArgs);
 
-template <int K, int O, int S>
+template <int K, int O, int S, int NW>
 PersistFn persist_fn_l(int lmax) {
-    if (K == KIND_SLIDE) return rlk::persist_kernel<KIND_SLIDE, O, S, 1, kNW>;
+    if (K == KIND_SLIDE) return rlk::persist_kernel<KIND_SLIDE, O, S, 1, NW>;
     switch (lmax) {
-        case 1: return rlk::persist_kernel<KIND_SPAN, O, S, 1, kNW>;
-        case 4: return rlk::persist_kernel<KIND_SPAN, O, S, 4, kNW>;
-        case 8: return rlk::persist_kernel<KIND_SPAN, O, S, 8, kNW>;
-        case 16: return rlk::persist_kernel<KIND_SPAN, O, S, 16, kNW>;
+        case 1: return rlk::persist_kernel<KIND_SPAN, O, S, 1, NW>;
+        case 4: return rlk::persist_kernel<KIND_SPAN, O, S, 4, NW>;
+        case 8: return rlk::persist_kernel<KIND_SPAN, O, S, 8, NW>;
+        case 16: return rlk::persist_kernel<KIND_SPAN, O, S, 16, NW>;
     }
     return nullptr;
 }
 
 template <int K, int O>
-PersistFn persist_fn_s(int S, int lmax) {
+PersistFn persist_fn_s(int S, int lmax, int nw) {
+    if (nw == 4) return S == 8 ? persist_fn_l<K, O, 8, 4>(lmax) : nullptr;
     switch (S) {
-        case 4: return persist_fn_l<K, O, 4>(lmax);
-        case 8: return persist_fn_l<K, O, 8>(lmax);
+        case 4: return persist_fn_l<K, O, 4, kNW>(lmax);
+        case 8: return persist_fn_l<K, O, 8, kNW>(lmax);
     }
     return nullptr;
 }
 
 PersistFn persist_fn(const Config& c) {
     if (c.kind == KIND_SPAN)
-        return c.orient == rlk::ORIENT_ROWS ? persist_fn_s<KIND_SPAN, rlk::ORIENT_ROWS>(c.S, c.lmax)
-                                            : persist_fn_s<KIND_SPAN, rlk::ORIENT_COLS>(c.S, c.lmax);
-    return c.orient == rlk::ORIENT_ROWS ? persist_fn_s<KIND_SLIDE, rlk::ORIENT_ROWS>(c.S, 0)
-                                        : persist_fn_s<KIND_SLIDE, rlk::ORIENT_COLS>(c.S, 0);
+        return c.orient == rlk::ORIENT_ROWS ? persist_fn_s<KIND_SPAN, rlk::ORIENT_ROWS>(c.S, c.lmax, c.nw)
+                                            : persist_fn_s<KIND_SPAN, rlk::ORIENT_COLS>(c.S, c.lmax, c.nw);
+    return c.orient == rlk::ORIENT_ROWS ? persist_fn_s<KIND_SLIDE, rlk::ORIENT_ROWS>(c.S, 0, c.nw)
+                                        : persist_fn_s<KIND_SLIDE, rlk::ORIENT_COLS>(c.S, 0, c.nw);
 }
 
 // Workgroups of a persistent kernel that the device holds at once.
-int persist_capacity(PersistFn fn, size_t lds) {
+int persist_capacity(PersistFn fn, size_t lds, int threads) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (lds > 64 * 1024) (void)allow_lds(reinterpret_cast<const void*>(fn), lds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
-                                                     kNW * 64, lds) != hipSuccess)
+                                                     threads, lds) != hipSuccess)
         return 0;
     return std::max(1, per_cu) * std::max(1, cus);
 }
@@ -1185,11 +1186,11 @@ rl_status enqueue_direct(rl_job* j, int32_t n) {
         const size_t lds = std::max(c.lds_a, c.lds_b);
         const int64_t tasks = (int64_t)2 * n * ntiles;
         if (tasks > ((int64_t)1 << 30)) return RL_E_UNSUPPORTED;
-        const int cap = persist_capacity(fn, lds);
+        const int cap = persist_capacity(fn, lds, c.threads);
         if (cap <= 0) return RL_E_DEVICE;
         const unsigned grid = (unsigned)std::min<int64_t>(cap, tasks);
         st = dev_err(launch(c.kind == KIND_SLIDE ? "persist_slide" : "persist_span", fn, dim3(grid),
-                            dim3(kNW * 64), lds, s, P), "persistent");
+                            dim3(c.threads), lds, s, P), "persistent");
         if (st) return st;
         j->k += n;
         j->persist_used = true;

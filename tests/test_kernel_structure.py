@@ -18,8 +18,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1304_7211_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# (KIND, ORIENT, S, LMAX): span kernels (KIND 0) with every LMAX, sliding kernels (KIND 1)
-VARIANTS = [(k, o, s, l) for k in (0, 1) for o in (0, 1) for s in (4, 8)
+# (KIND, ORIENT, S, LMAX, NW): span kernels (KIND 0) with every LMAX, sliding kernels
+# (KIND 1); eight wavefronts with strips of 4 and 8, four wavefronts with strips of 8
+VARIANTS = [(k, o, s, l, nw) for k in (0, 1) for o in (0, 1) for (s, nw) in ((4, 8), (8, 8), (8, 4))
             for l in ((1, 4, 8, 16) if k == 0 else (1,))]
 
 
@@ -48,8 +49,8 @@ def _barrier_depths(asm):
 def test_persistent_kernel_barriers_in_task_loop(tmp_path):
     src = tmp_path / "persist.hip"
     src.write_text('#include "rl_kernels.hpp"\n' + "".join(
-        f"template __global__ void rlk::persist_kernel<{k}, {o}, {s}, {l}, 8>(rlk::PersistArgs);\n"
-        for k, o, s, l in VARIANTS))
+        f"template __global__ void rlk::persist_kernel<{k}, {o}, {s}, {l}, {nw}>(rlk::PersistArgs);\n"
+        for k, o, s, l, nw in VARIANTS))
     asm = tmp_path / "persist.s"
     cmd = [HIPCC if os.path.exists(HIPCC) else "hipcc", "--offload-arch=gfx950", "-O3",
            "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
