@@ -325,7 +325,10 @@ rl_status rl_debug_spin_limit(int32_t polls, int32_t *previous);
 /* Kernel timing for measurement: while enabled, every kernel launch of every job is
  * bracketed by HIP events on the stream it is launched on.  rl_timing_read synchronises
  * on the recorded events and reports, for the kernel named `name`, the number of launches
- * and their summed duration in milliseconds; rl_timing_reset discards the records. */
+ * and their summed duration in milliseconds; rl_timing_reset discards the records.  While
+ * timing is on, rl_iterate_batch runs its kernel groups one after another on one stream
+ * (not concurrently), so that each recorded duration is the launch's own and not the time
+ * it shares the GPU with other groups; results are the same either way. */
 rl_status rl_timing_enable(int32_t on);
 rl_status rl_timing_read(const char *name, int64_t *launches, double *total_ms);
 rl_status rl_timing_reset(void);

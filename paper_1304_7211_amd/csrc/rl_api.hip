@@ -1894,7 +1894,14 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
     for (size_t ri = 0; ri < rgs.size(); ++ri) items.push_back(Item{rgs[ri].w, 1, (int)ri});
     for (int i : other) items.push_back(Item{resident_work_us(jobs[i], n_iter[i]), 2, i});
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.w > b.w; });
-    const int n_streams = std::min<int>(kBatchStreams, (int)items.size());
+    // with kernel timing on, everything runs on one side stream: each launch's events then
+    // bracket that launch alone, rather than the time it shares the GPU with the others
+    bool timing;
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        timing = g_timing;
+    }
+    const int n_streams = timing ? 1 : std::min<int>(kBatchStreams, (int)items.size());
     std::vector<double> load(n_streams, 0.0);
     std::vector<int> group_stream(gs.size(), 0), rgroup_stream(rgs.size(), 0);
     std::vector<std::pair<int, int>> other_stream;  // (job, stream)
