@@ -196,7 +196,11 @@ def roofline_of(kernels, work, traffic_fn):
         rf = dict(bound="hbm", achieved=round(hbm, 2), peak=PEAK_HBM_GBS, unit="GB/s",
                   frac=round(hbm / PEAK_HBM_GBS, 5), traffic=tr)
     else:
-        rf = dict(bound="alu", achieved=round(alu, 4), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+        # the matrix-core kernel is a float32 contraction on the matrix cores (bfloat16
+        # parts, float32 accumulation): its roof is the dense FP32 matrix peak, which on
+        # MI355X equals the packed FP32 vector peak
+        rf = dict(bound="mfma" if dom.startswith("mfma_") else "alu", achieved=round(alu, 4),
+                  peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                   frac=round(alu / PEAK_FP32_TFLOPS, 5), traffic=tr)
     rf.update(kernel=dom, launches=n, avg_us=round(kinfo["avg_us"], 3),
               total_ms=round(kinfo["total_ms"], 3),

@@ -152,3 +152,14 @@ def test_roofline_accounting():
     assert rf["bound"] == "alu" and rf["unit"] == "TFLOP/s"
     fl = (2 * 225 + 1) * px_it / 10
     assert abs(rf["frac"] - fl / 1e-6 / 1e12 / bench.PEAK_FP32_TFLOPS) < 1e-5
+
+
+def test_roofline_of_matrix_core_kernel():
+    """The matrix-core kernel's roof is the dense FP32 matrix peak (label "mfma")."""
+    import numpy as np
+    jobs = [dict(name="a", f=np.zeros((64, 64), np.float32), iters=10)]
+    infos = {"a": dict(schedule=1, path=6, lmax=0, n_spans=15, n_taps=225)}
+    work = bench.kernel_work(_FakeAbi, jobs, infos)
+    kernels = {"mfma_corr_update": dict(launches=10, total_ms=0.01, avg_us=1.0)}
+    rf = bench.roofline_of(kernels, work, lambda nm: None)
+    assert rf["bound"] == "mfma" and rf["peak"] == bench.PEAK_FP32_TFLOPS
