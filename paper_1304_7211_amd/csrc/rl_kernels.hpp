@@ -845,9 +845,15 @@ constexpr int MF_SPITCH = 84;        // row pitch (floats) of the float32 stagin
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// LDS: the three bfloat16 planes; the float32 staging tile lies inside their last part
+// (its rows are smaller than a row of the three planes) and is read into registers in full
+// before the planes are written, so a workgroup needs only the planes' LDS.
 __host__ __device__ constexpr size_t mfma_lds_bytes(int lines) {
-    return (size_t)(MF_T + lines - 1) * (3 * MF_PITCH * 2 + MF_SPITCH * 4);
+    return (size_t)(MF_T + lines - 1) * (3 * MF_PITCH * 2);
 }
+constexpr int MF_Q = MF_NX / 4;  // four-column groups per staged row
+constexpr int MF_MAXQ = ((MF_T + MF_MAXROWS - 1) * MF_Q + MF_NW * 64 - 1) / (MF_NW * 64);
+static_assert(MF_SPITCH * 4 <= 3 * MF_PITCH * 2, "staging rows must fit in plane rows");
 
 __device__ __forceinline__ void split3(float x, __bf16& p1, __bf16& p2, __bf16& p3) {
     p1 = (__bf16)x;
@@ -882,25 +888,40 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     const uint8_t own_c = blk_own_load<PHASE_B>(p, a0, b0);
 
     // source tile: float32 into LDS by DMA (load_tile: every row chunk in flight at once,
-    // boundary fold applied to the addresses), then converted in LDS into the three bfloat16
-    // planes, four consecutive values per thread and step
+    // boundary fold applied to the addresses) at the end of the planes' area, read into
+    // registers (four consecutive values per thread and step), then converted into the
+    // three bfloat16 planes, which overwrite the staging area
     const int ly0 = a0 + p.lane_min, lx0 = b0 + p.c_min;
-    float* stage = reinterpret_cast<float*>(lds + 3 * plane);
+    float* stage = reinterpret_cast<float*>(lds + 3 * plane) - ny * MF_SPITCH;
     load_tile(stage, p.src, p.H, p.W, p.bc, ly0, lx0, ny, MF_NX, MF_SPITCH);
     lds_dma_wait();
     __syncthreads();
-    for (int g = threadIdx.x; g < ny * (MF_NX / 4); g += MF_NW * 64) {
-        const int row = g / (MF_NX / 4), c4 = 4 * (g - row * (MF_NX / 4));
-        const float4 x = *reinterpret_cast<const float4*>(stage + row * MF_SPITCH + c4);
-        __bf16 a[4], b[4], c[4];
-        split3(x.x, a[0], b[0], c[0]);
-        split3(x.y, a[1], b[1], c[1]);
-        split3(x.z, a[2], b[2], c[2]);
-        split3(x.w, a[3], b[3], c[3]);
-        __bf16* d = lds + row * MF_PITCH + c4;
-        __builtin_memcpy(d, a, 8);
-        __builtin_memcpy(d + plane, b, 8);
-        __builtin_memcpy(d + 2 * plane, c, 8);
+    float4 xs[MF_MAXQ];
+#pragma unroll
+    for (int i = 0; i < MF_MAXQ; ++i) {
+        const int g = threadIdx.x + i * MF_NW * 64;
+        if (g < ny * MF_Q) {
+            const int row = g / MF_Q, c4 = 4 * (g - row * MF_Q);
+            xs[i] = *reinterpret_cast<const float4*>(stage + row * MF_SPITCH + c4);
+        }
+    }
+    __syncthreads();  // the staging area is read in full before the planes overwrite it
+#pragma unroll
+    for (int i = 0; i < MF_MAXQ; ++i) {
+        const int g = threadIdx.x + i * MF_NW * 64;
+        if (g < ny * MF_Q) {
+            const int row = g / MF_Q, c4 = 4 * (g - row * MF_Q);
+            const float4 x = xs[i];
+            __bf16 a[4], b[4], c[4];
+            split3(x.x, a[0], b[0], c[0]);
+            split3(x.y, a[1], b[1], c[1]);
+            split3(x.z, a[2], b[2], c[2]);
+            split3(x.w, a[3], b[3], c[3]);
+            __bf16* d = lds + row * MF_PITCH + c4;
+            __builtin_memcpy(d, a, 8);
+            __builtin_memcpy(d + plane, b, 8);
+            __builtin_memcpy(d + 2 * plane, c, 8);
+        }
     }
     __syncthreads();
 
