@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <string>
@@ -72,6 +73,7 @@ struct Layout {
     size_t f, u, r, conv_spans, conv_w, corr_spans, corr_w, mf_conv, mf_corr, cnt, plist, tflag, tlist,
         bcounts, boffs, ctr, sched, act, red, red_i, args, prefix, u2, fargs, done, pctl, tvg, wt,
         cntb, total;
+    size_t blob_end;  // [conv_spans, blob_end): the regions rl_init uploads from the host
 };
 
 // counters block (int64 slots)
@@ -577,6 +579,8 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     const size_t pad = 16;  // zero weights after the table (span kernel over-reads <= 15)
     // zero descriptors after each span table: the span and sliding kernels read up to
     // kSpanPad entries ahead
+    // the regions set from the host at rl_init (PSF tables, launch arguments, zeroed
+    // counters) lie together, so that one copy uploads them all
     L.conv_spans = take((cfg.conv.spans.size() + kSpanPad) * sizeof(DevSpan));
     L.conv_w = take((cfg.conv.w.size() + pad) * 4);
     L.corr_spans = take((cfg.corr.spans.size() + kSpanPad) * sizeof(DevSpan));
@@ -585,6 +589,12 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
         L.mf_conv = take(mfma_table_bytes(cfg.conv));
         L.mf_corr = take(mfma_table_bytes(cfg.corr));
     }
+    L.ctr = take(C_COUNT * 8);
+    L.args = take(2 * sizeof(PhaseArgs));
+    L.fargs = take(sizeof(rlk::FusedArgs));
+    L.prefix = take(2 * sizeof(int32_t));
+    L.pctl = take(2 * sizeof(int32_t));  // persistent launches: ticket, abort flag
+    L.blob_end = o;
     const size_t ntiles = (size_t)cfg.tiles_a * cfg.tiles_b;
     if (thin) {
         L.cnt = take(N);
@@ -598,15 +608,10 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
         const int lg = block_lg(p);
         L.cntb = lg ? take((size_t)block_count(p, lg)) : 0;  // block rule: one counter per block
     }
-    L.ctr = take(C_COUNT * 8);
-    L.args = take(2 * sizeof(PhaseArgs));
     L.u2 = cfg.kind == KIND_FUSED ? take(N * 4) : 0;
-    L.fargs = take(sizeof(rlk::FusedArgs));
-    L.prefix = take(2 * sizeof(int32_t));
     L.red = take(rlk::RED_BLOCKS * 8);
     L.red_i = take(rlk::RED_BLOCKS * 8);
     L.done = cfg.sched == RL_SCHED_PERSISTENT ? take(ntiles * 4) : 0;
-    L.pctl = take(2 * sizeof(int32_t));  // persistent launches: ticket, abort flag
     const bool rob = p->rob_eps > 0.f;
     L.tvg = (p->tv_lambda > 0.f || rob) ? take(N * 4) : 0;  // TV factor or robust h^* * w
     L.wt = rob ? take(N * 4) : 0;                           // robust weights w
@@ -657,6 +662,7 @@ struct rl_job {
     PhaseArgs h_args[2];
     int32_t h_prefix[2];
     rlk::FusedArgs h_fargs;
+    std::vector<char> h_blob;  // host image of [L.conv_spans, L.blob_end), uploaded by rl_init
     hipGraphExec_t graph = nullptr;  // captured chunk of graph_iters plain iterations
     int graph_n = 0;
     int graph_par = 0;  // parity of k the captured chunk starts at (fused schedule)
@@ -1313,6 +1319,64 @@ rl_status side_streams(int n) {
     return RL_OK;
 }
 
+// ---- pinned staging for host-to-device table uploads (rl_init, rl_iterate_batch) ------
+// A copy from pageable host memory may make the host wait for the stream: with a batch in
+// flight, creating the next batch's jobs would stall until the device drains, and the
+// device would then idle while the host sets the rest up.  The upload therefore goes
+// through pinned buffers, kept for reuse in upload order; a buffer is reused once the event
+// recorded after its copy has completed.  Buffers live until the process ends (at most
+// kPinCap bytes in all); beyond that, or if pinned memory is refused, the pageable copy
+// is used.
+struct PinBuf {
+    char* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    int dev = -1;
+};
+std::mutex g_pin_mu;
+std::deque<PinBuf> g_pin;  // oldest upload first
+size_t g_pin_bytes = 0;
+constexpr size_t kPinCap = size_t(256) << 20;
+constexpr size_t kPinMin = size_t(64) << 10;
+
+// Copy bytes from src to device address dst on stream s through a pinned buffer; false if
+// no buffer could be had (nothing was enqueued then).
+bool staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s, hipError_t* err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    PinBuf b;
+    bool found = false;
+    // the oldest few buffers are the likeliest to be free
+    for (size_t i = 0; i < g_pin.size() && i < 4; ++i) {
+        PinBuf& c = g_pin[i];
+        if (c.dev == dev && c.cap >= bytes && hipEventQuery(c.done) == hipSuccess) {
+            b = c;
+            g_pin.erase(g_pin.begin() + (std::ptrdiff_t)i);
+            found = true;
+            break;
+        }
+    }
+    if (!found) {
+        const size_t cap = std::max(kPinMin, (bytes + kPinMin - 1) / kPinMin * kPinMin);
+        if (g_pin_bytes + cap > kPinCap) return false;
+        if (hipHostMalloc((void**)&b.host, cap, hipHostMallocDefault) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(b.host);
+            return false;
+        }
+        b.cap = cap;
+        b.dev = dev;
+        g_pin_bytes += cap;
+    }
+    std::memcpy(b.host, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, b.host, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(b.done, s);
+    *err = e;
+    g_pin.push_back(b);  // after a failed enqueue the event still reports completion
+    return true;
+}
+
 struct BatchStage {
     std::vector<char> host;
     hipEvent_t done = nullptr;
@@ -1479,18 +1543,10 @@ rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, 
     j->h_conv_w.resize(j->h_conv_w.size() + 16, 0.f);
     j->h_corr_w = j->cfg.corr.w;
     j->h_corr_w.resize(j->h_corr_w.size() + 16, 0.f);
-    hipError_t e;
-    e = hipMemcpyAsync(j->at<void>(j->L.conv_spans), j->h_conv.data(), j->h_conv.size() * sizeof(DevSpan), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_spans), j->h_corr.data(), j->h_corr.size() * sizeof(DevSpan), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.conv_w), j->h_conv_w.data(), j->h_conv_w.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.corr_w), j->h_corr_w.data(), j->h_corr_w.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && j->cfg.kind == KIND_MFMA) {
+    if (j->cfg.kind == KIND_MFMA) {
         j->h_mf_conv = mfma_table(j->cfg.conv);
         j->h_mf_corr = mfma_table(j->cfg.corr);
-        e = hipMemcpyAsync(j->at<void>(j->L.mf_conv), j->h_mf_conv.data(), j->h_mf_conv.size() * 2, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.mf_corr), j->h_mf_corr.data(), j->h_mf_corr.size() * 2, hipMemcpyHostToDevice, s);
     }
-    if ((st = dev_err(e, "upload PSF"))) { delete j; return st; }
     if (j->cfg.kind == KIND_FUSED) {
         rlk::FusedArgs& a = j->h_fargs;
         a = rlk::FusedArgs{};
@@ -1514,24 +1570,49 @@ rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, 
         a.tiles_a = j->cfg.tiles_a;
         a.tiles_b = j->cfg.tiles_b;
         a.k = 0;
-        e = hipMemcpyAsync(j->at<void>(j->L.fargs), &j->h_fargs, sizeof j->h_fargs, hipMemcpyHostToDevice, s);
-        if ((st = dev_err(e, "upload fused args"))) { delete j; return st; }
     } else if (j->cfg.kind != KIND_RESIDENT) {
         j->h_args[0] = phase_args(j, false, 0);
         j->h_args[1] = phase_args(j, true, 0);
         j->h_prefix[0] = 0;
         j->h_prefix[1] = j->cfg.tiles_a * j->cfg.tiles_b;
-        e = hipMemcpyAsync(j->at<void>(j->L.args), j->h_args, sizeof j->h_args, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(j->at<void>(j->L.prefix), j->h_prefix, sizeof j->h_prefix, hipMemcpyHostToDevice, s);
-        if ((st = dev_err(e, "upload args"))) { delete j; return st; }
+    }
+    // one host image of every region set at init (tables, arguments, and the counters and
+    // persistent-launch words, which start at zero), one copy: each copy is a dependent
+    // operation on the stream, and a batch of many small jobs pays for every one of them
+    {
+        const size_t base = j->L.conv_spans;
+        std::vector<char>& b = j->h_blob;
+        b.assign(j->L.blob_end - base, 0);
+        auto put = [&](size_t at, const void* src, size_t bytes) {
+            if (bytes) std::memcpy(b.data() + (at - base), src, bytes);
+        };
+        put(j->L.conv_spans, j->h_conv.data(), j->h_conv.size() * sizeof(DevSpan));
+        put(j->L.corr_spans, j->h_corr.data(), j->h_corr.size() * sizeof(DevSpan));
+        put(j->L.conv_w, j->h_conv_w.data(), j->h_conv_w.size() * 4);
+        put(j->L.corr_w, j->h_corr_w.data(), j->h_corr_w.size() * 4);
+        if (j->cfg.kind == KIND_MFMA) {
+            put(j->L.mf_conv, j->h_mf_conv.data(), j->h_mf_conv.size() * 2);
+            put(j->L.mf_corr, j->h_mf_corr.data(), j->h_mf_corr.size() * 2);
+        }
+        if (j->cfg.kind == KIND_FUSED) {
+            put(j->L.fargs, &j->h_fargs, sizeof j->h_fargs);
+        } else if (j->cfg.kind != KIND_RESIDENT) {
+            put(j->L.args, j->h_args, sizeof j->h_args);
+            put(j->L.prefix, j->h_prefix, sizeof j->h_prefix);
+        }
+        hipError_t e = hipSuccess;
+        if (no_alloc || !staged_upload(j->at<void>(base), b.data(), b.size(), s, &e))
+            e = hipMemcpyAsync(j->at<void>(base), b.data(), b.size(), hipMemcpyHostToDevice, s);
+        if ((st = dev_err(e, "upload tables"))) { delete j; return st; }
     }
     const int64_t N = j->N;
-    unsigned g = grid_for(N);
-    if ((st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.f), p->f, N), "copy f"))) { delete j; return st; }
-    if ((st = dev_err(launch("copy_f32", rlk::copy_f32_kernel, dim3(g), dim3(256), 0, s, j->at<float>(j->L.u), p->u0 ? p->u0 : p->f, N), "copy u0"))) { delete j; return st; }
-    if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(g), dim3(256), 0, s, j->at<uint32_t>(j->L.r), 0u, N), "zero r"))) { delete j; return st; }
-    if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(1), dim3(256), 0, s, j->at<uint32_t>(j->L.ctr), 0u, (int64_t)C_COUNT * 2), "zero ctr"))) { delete j; return st; }
-    if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(1), dim3(256), 0, s, j->at<uint32_t>(j->L.pctl), 0u, (int64_t)2), "zero pctl"))) { delete j; return st; }
+    // f and u^0 into the workspace, r = 0, and the check of f (negative, NaN or infinite
+    // values set the invalid flag), in one pass
+    if ((st = dev_err(launch("init_fields", rlk::init_fields_kernel, dim3(grid_for(N)), dim3(256), 0, s,
+                             j->at<float>(j->L.f), j->at<float>(j->L.u), j->at<float>(j->L.r), p->f,
+                             p->u0 ? p->u0 : p->f, N,
+                             reinterpret_cast<int32_t*>(j->at<int64_t>(j->L.ctr) + C_F_INVALID)),
+                      "init fields"))) { delete j; return st; }
     if (p->thin.mode != RL_THIN_OFF) {
         int64_t nt = (int64_t)j->cfg.tiles_a * j->cfg.tiles_b;
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(N / 4 + 1)), dim3(256), 0, s, j->at<uint32_t>(j->L.cnt), 0u, (N + 3) / 4), "zero cnt"))) { delete j; return st; }
@@ -1546,8 +1627,6 @@ rl_status init_job(const rl_params* p, void* ws, size_t ws_bytes, rl_job** out, 
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(grid_for(rlk::SCHED_RING * 2)), dim3(256), 0, s, j->at<uint32_t>(j->L.sched), 0u, (int64_t)rlk::SCHED_RING * 2), "zero ring"))) { delete j; return st; }
         if ((st = dev_err(launch("fill_u32", rlk::fill_u32_kernel, dim3(2), dim3(256), 0, s, j->at<uint32_t>(j->L.act), 0u, (int64_t)2 * rlk::ACT_SLOTS), "zero act"))) { delete j; return st; }
     }
-    if ((st = dev_err(launch("check_f", rlk::check_f_kernel, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s,
-                             (const float*)j->at<float>(j->L.f), N, reinterpret_cast<int32_t*>(j->at<int64_t>(j->L.ctr) + C_F_INVALID)), "check f"))) { delete j; return st; }
     if (p->thin.mode != RL_THIN_OFF && !no_alloc) {
         // pinned word and event for the asynchronous active-tile count (optional: without
         // them the tile list is always used)
@@ -1870,8 +1949,9 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
             for (size_t q = 0; q < g.idx.size(); ++q) t[q] = resident_args(jobs[g.idx[q]], n_iter[g.idx[q]]);
             std::memcpy(bs.host.data() + g.off_p, g.prefix.data(), g.prefix.size() * sizeof(int32_t));
         }
-        hipError_t e = off ? hipMemcpyAsync(bws, bs.host.data(), off, hipMemcpyHostToDevice, s)
-                           : hipSuccess;
+        hipError_t e = hipSuccess;
+        if (off && !staged_upload(bws, bs.host.data(), off, s, &e))
+            e = hipMemcpyAsync(bws, bs.host.data(), off, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipEventRecord(bs.done, s);
         if ((st = dev_err(e, "batch tables"))) return st;
         bs.pending = true;

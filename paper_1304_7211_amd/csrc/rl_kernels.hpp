@@ -2394,12 +2394,20 @@ __global__ __launch_bounds__(256) void robust_weights_kernel(float* r, const flo
     }
 }
 
-__global__ __launch_bounds__(256) void check_f_kernel(const float* f, int64_t N, int32_t* flag) {
+// Job set-up in one pass: f and u^0 into the workspace, r = 0, and the check of f (the
+// observed image must be non-negative and finite; a wavefront that meets a negative, NaN
+// or infinite value sets *flag).  u0 may be f itself.
+__global__ __launch_bounds__(256) void init_fields_kernel(float* wf, float* wu, float* wr,
+                                                          const float* f, const float* u0,
+                                                          int64_t N, int32_t* flag) {
     int bad = 0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * 256) {
-        float v = f[p];
+        const float v = f[p];
         if (!(v >= 0.f) || isinf(v)) bad = 1;
+        wf[p] = v;
+        wu[p] = u0[p];
+        wr[p] = 0.f;
     }
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
