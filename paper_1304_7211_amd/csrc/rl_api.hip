@@ -1371,9 +1371,16 @@ bool staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s, hipE
     }
     std::memcpy(b.host, src, bytes);
     hipError_t e = hipMemcpyAsync(dst, b.host, bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(b.done, s);
     *err = e;
-    g_pin.push_back(b);  // after a failed enqueue the event still reports completion
+    if (e != hipSuccess) {
+        g_pin.push_back(b);  // nothing in flight: the event still reports its last state
+        return true;
+    }
+    e = hipEventRecord(b.done, s);
+    *err = e;
+    // a copy in flight without its event could not be told apart from a finished one: such
+    // a buffer is not reused
+    if (e == hipSuccess) g_pin.push_back(b);
     return true;
 }
 
