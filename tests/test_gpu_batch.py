@@ -109,3 +109,25 @@ def test_batch_errors():
         runner.iterate([job], [-1])
     assert e.value.status == A.RL_E_INVAL
     job.close()
+
+
+def test_jobs_set_up_while_a_batch_runs():
+    """Jobs created while earlier batches still run (their table uploads go through pinned
+    buffers that the library reuses once their copies have completed) end bit-identical to
+    the same jobs run alone on an idle device, round after round."""
+    specs = _mixed_jobs()
+    alone = [_alone(f, h, kw, K)[0] for (_, f, h, kw, K) in specs]
+    fs = [to_dev(f) for (_, f, *_r) in specs]
+    runner = BatchRunner(len(specs))
+    rounds = []
+    for _ in range(3):
+        # no synchronisation: each round's jobs are set up behind the previous round's batch
+        jobs = [Job(fd, h, **kw) for fd, (_, f, h, kw, K) in zip(fs, specs)]
+        runner.iterate(jobs, [K for (*_, K) in specs])
+        rounds.append([j.result() for j in jobs])
+        for j in jobs:
+            j.close()
+    torch.cuda.synchronize()
+    for outs in rounds:
+        for (name, *_r), o, u_a in zip(specs, outs, alone):
+            assert np.array_equal(o.cpu().numpy(), u_a), name
