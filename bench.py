@@ -62,7 +62,7 @@ import numpy as np  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 # FP32 vector peak of MI355X: 256 CUs x 128 FP32 lanes (packed) x 2 flops (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
-# the same without packed FP32 instructions (switched off in this build): 64 lanes per CU
+# the same without packed FP32 instructions (the library is compiled without them): 64 lanes per CU
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 
 

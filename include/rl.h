@@ -50,7 +50,7 @@ typedef int32_t rl_status;
 #define RL_E_NOMEM (-2)       /* workspace too small                                      */
 #define RL_E_DEVICE (-3)      /* a HIP runtime call failed                                */
 #define RL_E_STATE (-4)       /* call not allowed in this state (e.g. after destroy)      */
-#define RL_E_UNSUPPORTED (-5) /* valid request this build does not serve                  */
+#define RL_E_UNSUPPORTED (-5) /* valid request the library does not serve                 */
 
 /* boundary continuation */
 #define RL_BC_REFLECT 0
