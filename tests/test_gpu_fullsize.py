@@ -10,7 +10,11 @@ Specialised PSFs (three 1024 x 1024 jobs advanced by one rl_iterate_batch call):
   only point-symmetric, so it is exempt).
 Batched workload (256 uneven jobs, mixed PSFs, one rl_iterate_batch call, compensated
 sums): the full-length results of the two cheapest jobs of each PSF class against the
-FP64 oracle (RTOL).
+FP64 oracle (RTOL); for the largest job of each class (up to 2048 x 2048), whose full
+length the oracle cannot run in seconds, the last iteration of the batch in lock step
+(the oracle's step from the GPU's own u^{K-1}, RTOL); for all 256 jobs, finite and
+non-negative results and the flux of f kept where the PSF has odd sides and is
+mirror-symmetric in both axes.
 """
 import numpy as np
 import pytest
@@ -80,6 +84,46 @@ def test_batched_full_length_against_oracle(orc):
         ref = orc.rl(j["f"], j["psf"], j["iters"])
         err = rel_err(outs[i], ref)
         print(f"{j['name']} {j['f'].shape} K={j['iters']}: err {err:.3g}", flush=True)
+        assert err <= RTOL, (j["name"], err)
+
+
+def test_batched_largest_jobs_last_step_and_properties(orc):
+    import bench
+    jobs = synth.job_for_config(4, workers=8)
+    largest = {}
+    for i, j in enumerate(jobs):
+        cls = j["name"].split("-")[1]
+        if cls not in largest or j["f"].size > jobs[largest[cls]]["f"].size:
+            largest[cls] = i
+    assert sorted(largest) == ["axis", "dense", "disc", "oblique"]
+    fs = [to_dev(j["f"]) for j in jobs]
+    js = [Job(f, j["psf"], kahan=True) for j, f in zip(jobs, fs)]
+    runner = BatchRunner(len(js))
+    # the batch as the benchmark runs it, in two calls: K - 1 iterations, then the last one
+    runner.iterate(js, [j["iters"] - 1 for j in jobs])
+    prev = {i: js[i].get_state()["u"].cpu().numpy() for i in largest.values()}
+    runner.iterate(js, [1] * len(js))
+    res = [jb.result(stats=True) for jb in js]
+    for (u, st), j in zip(res, jobs):
+        assert st.iters_done == j["iters"]
+        un = u.cpu().numpy()
+        assert np.isfinite(un).all() and (un >= 0).all(), j["name"]
+        h = j["psf"]
+        # an even side puts the anchor off the centre: mirror symmetry of the array is then
+        # not symmetry of the operator, and the folded correlation is not the adjoint
+        odd = h.shape[0] % 2 == 1 and h.shape[1] % 2 == 1
+        if odd and np.array_equal(h, h[::-1, :]) and np.array_equal(h, h[:, ::-1]):
+            fsum = float(j["f"].astype(np.float64).sum())
+            assert abs(st.flux - fsum) <= 1e-5 * fsum, (j["name"], st.flux, fsum)
+    last = {i: res[i][0].cpu().numpy() for i in largest.values()}
+    for jb in js:
+        jb.close()
+    del fs
+    for cls, i in sorted(largest.items()):
+        j = jobs[i]
+        ref = orc.rl(j["f"], j["psf"], 1, u0=prev[i].astype(np.float64))
+        err = rel_err(last[i], ref)
+        print(f"{j['name']} {j['f'].shape} step {j['iters']}: err {err:.3g}", flush=True)
         assert err <= RTOL, (j["name"], err)
 
 
