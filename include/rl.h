@@ -207,6 +207,10 @@ rl_status rl_workspace_bytes(const rl_params *p, size_t *bytes);
  * it must stay alive and untouched until rl_destroy.  f's sign and finiteness are checked
  * on the GPU; the outcome is reported by rl_result (RL_E_INVAL) and in rl_stats.f_invalid.
  * On success *out receives a new job handle (host memory owned by the library).
+ * The upload goes through pinned host buffers that the library allocates on first need,
+ * reuses once their copies have completed and keeps until the process ends (at most
+ * 256 MiB in all, then pageable copies), so that rl_init does not wait for work already
+ * on the stream; rl_iterate_batch uploads its tables the same way.
  * Errors: RL_E_INVAL (sizes, PSF, NULL pointers, path not applicable to the PSF),
  * RL_E_NOMEM (ws_bytes too small), RL_E_DEVICE.
  */
