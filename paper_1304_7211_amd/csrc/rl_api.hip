@@ -41,6 +41,9 @@ constexpr int kNW = 8;  // wavefronts per workgroup in the tiled kernels
 // 1 where eight wavefronts would run strips of 4 (images below 0.5 Mpx), 2 also in place of
 // strips of 8 (64 x 32 tiles on every image)
 constexpr int kFourWave = 1;
+// wavefronts per workgroup of the matrix-core kernel: a job's own launches, batch launches
+constexpr int kMfmaNW = 8;
+constexpr int kMfmaBatchNW = 4;
 constexpr size_t kSpanPad = 2;  // zero descriptors after each span table (read-ahead)
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
@@ -472,7 +475,12 @@ rl_status choose_config_raw(const rl_params* p, const rl::CompiledPsf& c, Config
     }
     cfg->TA = 64;
     cfg->TB = cfg->kind == KIND_MFMA ? rlk::MF_T : cfg->nw * cfg->S;
-    if (cfg->kind == KIND_MFMA) cfg->threads = rlk::MF_NW * 64;
+    if (cfg->kind == KIND_MFMA) {
+        // a job's own launches: eight wavefronts per tile (rl_iterate_batch runs its matrix-core
+        // groups with four, kMfmaBatchNW; the results are the same)
+        cfg->nw = kMfmaNW;
+        cfg->threads = kMfmaNW * 64;
+    }
     const int extra = 0;  // windows never read past the last tap of a piece
     auto lds_for = [&](const rl::OpTable& t) {
         size_t b = tile_lds_bytes(t, cfg->orient, cfg->TB, extra);
@@ -837,7 +845,10 @@ std::atomic<int> g_spin_limit{kSpinLimit};  // rl_debug_spin_limit changes it fo
 rl_status check_persist_abort(rl_job* j, hipStream_t s);
 
 PhaseFn phase_fn(const Config& c, bool phase_b) {
-    if (c.kind == KIND_MFMA) return phase_b ? rlk::mfma_kernel<true> : rlk::mfma_kernel<false>;
+    if (c.kind == KIND_MFMA) {
+        if (c.nw == 8) return phase_b ? rlk::mfma_kernel<8, true> : rlk::mfma_kernel<8, false>;
+        return phase_b ? rlk::mfma_kernel<4, true> : rlk::mfma_kernel<4, false>;
+    }
     if (c.kind == KIND_RECT) {
         if (c.S == 4) return phase_b ? rlk::rect_kernel<4, kNW, true> : rlk::rect_kernel<4, kNW, false>;
         if (c.S == 8) return phase_b ? rlk::rect_kernel<8, kNW, true> : rlk::rect_kernel<8, kNW, false>;
@@ -1885,7 +1896,13 @@ rl_status rl_iterate_batch(rl_job* const* jobs, const int32_t* n_iter, int32_t n
             g.lds_a = std::max(g.lds_a, c.lds_a);
             g.lds_b = std::max(g.lds_b, c.lds_b);
         }
-        const Config& c0 = jobs[g.idx[0]]->cfg;
+        Config c0 = jobs[g.idx[0]]->cfg;
+        if (c0.kind == KIND_MFMA) {
+            // batch launches of the matrix-core kernel: four wavefronts per tile, so that more
+            // tiles share a CU while the other groups' launches overlap
+            c0.nw = kMfmaBatchNW;
+            c0.threads = kMfmaBatchNW * 64;
+        }
         g.threads = c0.threads;
         g.fa = phase_fn(c0, false);
         g.fb = phase_fn(c0, true);

@@ -823,9 +823,14 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 // and odd lines go into two accumulators, the five smaller ones into a third; the output is
 // (even + odd) + small.  A window whose inputs are all zero gives exactly zero.
 //
-// A workgroup of MF_NW wavefronts owns a 64 x 64 output tile; wavefront w computes rows
-// 16 w .. 16 w + 15 as four 16 x 16 blocks side by side, which share each line's weight
-// operand.  The source tile (PSF halo included, boundary fold applied) is converted once
+// A workgroup of NW wavefronts owns a 64 x 64 output tile.  With NW = 4 wavefront w
+// computes rows 16 w .. 16 w + 15 as four 16 x 16 blocks side by side, which share each
+// line's weight operand; with NW = 8 wavefront w computes two such blocks, rows
+// 16 (w % 4) .., columns 32 (w / 4) ...  Every block sees the same sequence of products
+// either way, so both give identical results: eight wavefronts finish a tile sooner (a
+// single job's launch at 1 Mpx: 10.6 against 12.7-13.2 us), four keep more tiles per CU
+// (a batch of many jobs, whose launches overlap on several streams, 395-403 against
+// 407-417 ms).  The source tile (PSF halo included, boundary fold applied) is converted once
 // into three bfloat16 planes in LDS with a row pitch of MF_PITCH elements (10 x 16 bytes,
 // the unpadded row: of the pitches 80 .. 136 measured, 80 gave the fewest LDS bank-conflict
 // cycles on the operand loads, a ninth of those of 88).  Operand layout of v_mfma_f32_16x16x32_bf16 on a wavefront of 64: lane l
@@ -834,7 +839,6 @@ __global__ __launch_bounds__(NW * 64) void span_kernel(LaunchArgs L) {
 // 8 bfloat16 values) are built on the host; p.wts points to them.  The epilogue is the
 // one of the other phase kernels (ratio or update, thinning counters, TV, robust store).
 // ---------------------------------------------------------------------------------------
-constexpr int MF_NW = 4;
 constexpr int MF_T = 64;             // tile rows and columns
 constexpr int MF_NX = MF_T + 16;     // LDS columns: the last block reads 16 * 3 + 32
 constexpr int MF_PITCH = 80;         // LDS row pitch in bfloat16 elements
@@ -852,7 +856,10 @@ __host__ __device__ constexpr size_t mfma_lds_bytes(int lines) {
     return (size_t)(MF_T + lines - 1) * (3 * MF_PITCH * 2);
 }
 constexpr int MF_Q = MF_NX / 4;  // four-column groups per staged row
-constexpr int MF_MAXQ = ((MF_T + MF_MAXROWS - 1) * MF_Q + MF_NW * 64 - 1) / (MF_NW * 64);
+// staged four-column groups per thread (at most), for a workgroup of NW wavefronts
+__host__ __device__ constexpr int mf_maxq(int nw) {
+    return ((MF_T + MF_MAXROWS - 1) * MF_Q + nw * 64 - 1) / (nw * 64);
+}
 static_assert(MF_SPITCH * 4 <= 3 * MF_PITCH * 2, "staging rows must fit in plane rows");
 
 __device__ __forceinline__ void split3(float x, __bf16& p1, __bf16& p2, __bf16& p3) {
@@ -862,8 +869,11 @@ __device__ __forceinline__ void split3(float x, __bf16& p1, __bf16& p2, __bf16& 
     p3 = (__bf16)(r1 - (float)p2);
 }
 
-template <bool PHASE_B>
-__global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
+template <int NW, bool PHASE_B>
+__global__ __launch_bounds__(NW * 64) void mfma_kernel(LaunchArgs L) {
+    static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
+    constexpr int BPW = 16 / NW;  // 16 x 16 blocks per wavefront
+    constexpr int MAXQ = mf_maxq(NW);
     extern __shared__ float lds_f[];
     __bf16* lds = reinterpret_cast<__bf16*>(lds_f);
     int a0, b0;
@@ -871,17 +881,18 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     if (!resolve<PHASE_B>(L, p, MF_T, MF_T, a0, b0)) return;
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int m = lane & 15, q = lane >> 4;
+    const int wr = wv & 3, wc = wv >> 2;  // row group and column group of this wavefront
     const int lines = p.lane_max - p.lane_min + 1;
     const int ny = MF_T + lines - 1;
     const int plane = ny * MF_PITCH;
 
     // epilogue inputs of this lane's 16 outputs, loaded before the tile so they overlap it
-    EpiIn ein[4][4];
+    EpiIn ein[BPW][4];
 #pragma unroll
-    for (int bx = 0; bx < 4; ++bx)
+    for (int bx = 0; bx < BPW; ++bx)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int y = a0 + 16 * wv + 4 * q + t, x = b0 + 16 * bx + m;
+            const int y = a0 + 16 * wr + 4 * q + t, x = b0 + 16 * (BPW * wc + bx) + m;
             if (y < p.H && x < p.W) ein[bx][t] = epi_load<PHASE_B>(p, y, x, (size_t)y * p.W + x);
         }
 
@@ -896,10 +907,10 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     load_tile(stage, p.src, p.H, p.W, p.bc, ly0, lx0, ny, MF_NX, MF_SPITCH);
     lds_dma_wait();
     __syncthreads();
-    float4 xs[MF_MAXQ];
+    float4 xs[MAXQ];
 #pragma unroll
-    for (int i = 0; i < MF_MAXQ; ++i) {
-        const int g = threadIdx.x + i * MF_NW * 64;
+    for (int i = 0; i < MAXQ; ++i) {
+        const int g = threadIdx.x + i * NW * 64;
         if (g < ny * MF_Q) {
             const int row = g / MF_Q, c4 = 4 * (g - row * MF_Q);
             xs[i] = *reinterpret_cast<const float4*>(stage + row * MF_SPITCH + c4);
@@ -907,8 +918,8 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     }
     __syncthreads();  // the staging area is read in full before the planes overwrite it
 #pragma unroll
-    for (int i = 0; i < MF_MAXQ; ++i) {
-        const int g = threadIdx.x + i * MF_NW * 64;
+    for (int i = 0; i < MAXQ; ++i) {
+        const int g = threadIdx.x + i * NW * 64;
         if (g < ny * MF_Q) {
             const int row = g / MF_Q, c4 = 4 * (g - row * MF_Q);
             const float4 x = xs[i];
@@ -925,24 +936,24 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     }
     __syncthreads();
 
-    f32x4 even[4], odd[4], small[4];
+    f32x4 even[BPW], odd[BPW], small[BPW];
 #pragma unroll
-    for (int bx = 0; bx < 4; ++bx)
+    for (int bx = 0; bx < BPW; ++bx)
         for (int t = 0; t < 4; ++t) even[bx][t] = odd[bx][t] = small[bx][t] = 0.f;
     // weight operands: each line's are loaded one line ahead (the table carries one zero
     // line past its end), so their round trip overlaps the previous line's products
     const bf16x8* tab = reinterpret_cast<const bf16x8*>(p.wts);
     bf16x8 nw1 = tab[lane], nw2 = tab[64 + lane], nw3 = tab[128 + lane];
-    const __bf16* base = lds + (16 * wv + m) * MF_PITCH + 8 * q;
+    const __bf16* base = lds + (16 * wr + m) * MF_PITCH + 8 * q + 16 * BPW * wc;
     // one PSF line: its leading products into acc, the five smaller ones into small
-    auto line = [&](int di, f32x4 (&acc)[4]) {
+    auto line = [&](int di, f32x4 (&acc)[BPW]) {
         const bf16x8 w1 = nw1, w2 = nw2, w3 = nw3;
         nw1 = tab[(3 * di + 3) * 64 + lane];
         nw2 = tab[(3 * di + 4) * 64 + lane];
         nw3 = tab[(3 * di + 5) * 64 + lane];
         const __bf16* rp = base + di * MF_PITCH;
 #pragma unroll
-        for (int bx = 0; bx < 4; ++bx) {
+        for (int bx = 0; bx < BPW; ++bx) {
             const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(rp + 16 * bx);
             const bf16x8 x2 = *reinterpret_cast<const bf16x8*>(rp + plane + 16 * bx);
             const bf16x8 x3 = *reinterpret_cast<const bf16x8*>(rp + 2 * plane + 16 * bx);
@@ -969,10 +980,10 @@ __global__ __launch_bounds__(MF_NW * 64) void mfma_kernel(LaunchArgs L) {
     int n_active = 0;
     uint64_t fails = 0;
 #pragma unroll
-    for (int bx = 0; bx < 4; ++bx)
+    for (int bx = 0; bx < BPW; ++bx)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int y = a0 + 16 * wv + 4 * q + t, x = b0 + 16 * bx + m;
+            const int y = a0 + 16 * wr + 4 * q + t, x = b0 + 16 * (BPW * wc + bx) + m;
             const float v = (even[bx][t] + odd[bx][t]) + small[bx][t];
             int act = 0;
             if (y < p.H && x < p.W)

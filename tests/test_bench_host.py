@@ -46,8 +46,8 @@ def test_timing_names():
     assert n("void rlk::resident_kernel<1, 8>(rlk::ResidentArgs)") == "resident_box"
     assert n("void rlk::resident_multi_kernel<0, 16>(rlk::ResidentArgs const*, int const*, int)") \
         == "resident_box"
-    assert n("void rlk::mfma_kernel<true>(rlk::LaunchArgs)") == "mfma_corr_update"
-    assert n("void rlk::mfma_kernel<false>(rlk::LaunchArgs)") == "mfma_conv_ratio"
+    assert n("void rlk::mfma_kernel<8, true>(rlk::LaunchArgs)") == "mfma_corr_update"
+    assert n("void rlk::mfma_kernel<4, false>(rlk::LaunchArgs)") == "mfma_conv_ratio"
     assert n("__amd_rocclr_copyBuffer") is None
 
 
