@@ -153,6 +153,9 @@ def test_mfma_tv_and_robust(orc):
 
 
 def test_mfma_in_a_batch_is_bit_identical_to_alone():
+    """Batch launches run the kernel with four wavefronts per tile, a job's own launches with
+    eight (two blocks per wavefront instead of four): every block sees the same products in
+    the same order, so the two shapes must agree bit for bit."""
     specs = [(synth.dense_random(15, 31), (300, 257), 12), (synth.disc(5), (128, 200), 9),
              (synth.dense_random(15, 32), (97, 131), 17), (synth.oblique_line(21, 60.0), (150, 150), 5)]
     fs = [to_dev(_obs(H, W, h, 40 + i)) for i, (h, (H, W), _) in enumerate(specs)]
