@@ -280,7 +280,14 @@ def main():
                     help="no GPU work: turn a rocprofv3 --kernel-trace --stats CSV output "
                          "and the JSON line of an unprofiled bench run into the kernel "
                          "trace summary (markdown) on stdout")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="no GPU work: turn rocprofv3 --pmc CSV outputs of SQ counters "
+                         "(SQ_WAVES among them) into per-wavefront averages per kernel "
+                         "symbol (markdown) on stdout")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.pmc_command))
+        return
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
                             args.calibrate_copy, args.pmc_command, args.summary_side,
@@ -851,6 +858,56 @@ def summarize_trace(trace_dir, bench_log, command, side=0, workload="batched"):
             f"{rf.get('achieved')} {rf.get('unit')} = {rf.get('frac')} of {rf.get('peak')} "
             f"(bound {rf.get('bound')})."]
     return "\n".join(out)
+
+
+def summarize_counters(dirs, command, min_waves=1000):
+    """Per kernel symbol, each counter's per-dispatch total (summed over the dispatch's
+    shader engines) divided by the dispatch's wavefronts (SQ_WAVES), averaged over
+    dispatches; SQ_WAVES itself per dispatch.  Kernels with fewer than min_waves
+    wavefronts per dispatch are left out."""
+    import csv
+    import glob
+    import re
+    tot, disp = {}, {}
+    for d in dirs:
+        fn = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        for r in csv.DictReader(open(fn)):
+            k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+            c = r["Counter_Name"]
+            tot.setdefault(k, {}).setdefault(c, 0.0)
+            tot[k][c] += float(r["Counter_Value"])
+            disp.setdefault(k, {}).setdefault(c, set()).add(r["Dispatch_Id"])
+    order = ["SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
+             "SQ_ACTIVE_INST_VALU", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_WAIT_INST_LDS",
+             "SQ_WAIT_INST_ANY", "SQ_LDS_BANK_CONFLICT", "SQ_WAVE_CYCLES"]
+    present = {c for k in tot for c in tot[k]}
+    counters = [c for c in order if c in present] + sorted(present - set(order) - {"SQ_WAVES"})
+    lines = ["# Instruction mix per wavefront: kernels of the batched workload", "",
+             "Commands (one pass per counter group; rocprofv3 does not split counters over "
+             "passes):", "", "```", command, "```", "",
+             "Per kernel symbol: SQ_WAVES per dispatch, and every other counter's total over a "
+             "dispatch divided by that dispatch's wavefronts (averaged over dispatches).  "
+             "`SQ_INSTS_*` count instructions; `SQ_WAIT_INST_*`, `SQ_LDS_BANK_CONFLICT` and "
+             "`SQ_VALU_MFMA_BUSY_CYCLES` count cycles.", "",
+             "| Kernel | dispatches | waves | " + " | ".join(counters) + " |",
+             "|---|---|---|" + "---|" * len(counters)]
+    rows = []
+    for k, cs in tot.items():
+        if "SQ_WAVES" not in cs:
+            continue
+        nd = len(disp[k]["SQ_WAVES"])
+        waves = cs["SQ_WAVES"] / nd
+        if waves < min_waves:
+            continue
+        vals = []
+        for c in counters:
+            if c in cs:
+                vals.append(f"{cs[c] / len(disp[k][c]) / waves:.0f}")
+            else:
+                vals.append("")
+        rows.append((-(cs.get("SQ_WAVES", 0.0)), f"| `{k}` | {nd} | {waves:.0f} | " + " | ".join(vals) + " |"))
+    lines += [r for _, r in sorted(rows)]
+    return "\n".join(lines)
 
 
 def summarize_pmc(fetch_dir, write_dir, copy_mib, command, side=0, workload="batched"):

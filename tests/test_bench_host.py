@@ -163,3 +163,25 @@ def test_roofline_of_matrix_core_kernel():
     kernels = {"mfma_corr_update": dict(launches=10, total_ms=0.01, avg_us=1.0)}
     rf = bench.roofline_of(kernels, work, lambda nm: None)
     assert rf["bound"] == "mfma" and rf["peak"] == bench.PEAK_FP32_TFLOPS
+
+
+def test_summarize_counters_per_wavefront(tmp_path):
+    """Each counter's per-dispatch total divided by the dispatch's wavefronts; SQ_WAVES
+    from the pass that has it, small kernels left out."""
+    d1, d2 = tmp_path / "a", tmp_path / "b"
+    k = "void rlk::span_kernel<0, 8, 8, 8, false>(rlk::LaunchArgs)"
+    for d, rows in ((d1, [("SQ_WAVES", 1, 1000.0), ("SQ_WAVES", 1, 1000.0), ("SQ_INSTS_VALU", 1, 5e5),
+                          ("SQ_INSTS_VALU", 1, 7e5), ("SQ_WAVES", 2, 2000.0), ("SQ_INSTS_VALU", 2, 2e6)]),
+                    (d2, [("SQ_INSTS_SALU", 1, 1e6), ("SQ_INSTS_SALU", 2, 3e6)])):
+        os.makedirs(d)
+        with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+            w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                               "Counter_Value"])
+            w.writeheader()
+            for c, disp, v in rows:
+                w.writerow(dict(Dispatch_Id=disp, Kernel_Name=k, Counter_Name=c, Counter_Value=v))
+    text = bench.summarize_counters([str(d1), str(d2)], "cmd")
+    row = [l for l in text.splitlines() if "span_kernel" in l][0]
+    # 2 dispatches, 2000 wavefronts each on average (one of them summed over two engines);
+    # VALU 1.2e6 + 2e6 over two dispatches / 2000 = 800; SALU 4e6 / 2 / 2000 = 1000
+    assert row == "| `rlk::span_kernel<0, 8, 8, 8, false>` | 2 | 2000 | 800 | 1000 |"
