@@ -584,11 +584,11 @@ Layout make_layout(const rl_params* p, const Config& cfg) {
     L.f = take(N * 4);
     L.u = take(N * 4);
     L.r = take(N * 4);
+    // the regions set from the host at rl_init (PSF tables, launch arguments, zeroed
+    // counters) lie together, so that one copy uploads them all
     const size_t pad = 16;  // zero weights after the table (span kernel over-reads <= 15)
     // zero descriptors after each span table: the span and sliding kernels read up to
     // kSpanPad entries ahead
-    // the regions set from the host at rl_init (PSF tables, launch arguments, zeroed
-    // counters) lie together, so that one copy uploads them all
     L.conv_spans = take((cfg.conv.spans.size() + kSpanPad) * sizeof(DevSpan));
     L.conv_w = take((cfg.conv.w.size() + pad) * 4);
     L.corr_spans = take((cfg.corr.spans.size() + kSpanPad) * sizeof(DevSpan));
